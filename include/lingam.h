@@ -1,0 +1,150 @@
+/*
+ * lingam.h -- C ABI of the MI355X (gfx950) DirectLiNGAM causal-order search.
+ *
+ * The library finds the causal order K of a linear non-Gaussian acyclic model
+ * from observational data, the first (order-finding) step of DirectLiNGAM
+ * that ParaLiNGAM accelerates (Shahbazinia, Salehkaleybar, Hashemi,
+ * "ParaLiNGAM", arXiv 2109.13993):
+ *   - Alg. 1 lines 1-7 / Alg. 3: p iterations of "find the root, append it to
+ *     K, remove it from U, regress it out of the remaining variables";
+ *   - Alg. 2: the root is the variable of minimum score
+ *     S_i = sum_j min(0, I(x_i, x_j, r_i^(j), r_j^(i)))^2, with the
+ *     likelihood-ratio test of Eq. (Itest) and the entropy approximation of
+ *     Eq. (HApp); this library reports T_i = -S_i (root = argmax T);
+ *   - Sec. 3.1 (messaging): each unordered pair is evaluated once and the
+ *     reverse test is its exact negation;
+ *   - Sec. 3.2-3.3 (threshold): variables whose partial score exceeds a
+ *     threshold gamma stop comparing; gamma is multiplied by c until the
+ *     iteration can end.  The order is the same as without the threshold;
+ *   - Sec. 3.4 (Eq. var_update, Eq. CovUpdate, UpdateData, UpdateCovMat):
+ *     normalisation once, covariance once, then rank-1 updates of the data
+ *     and of the covariance after every root.
+ *
+ * Every symbol is extern "C".  No C++ exception crosses the ABI.  All calls
+ * are synchronous: they return once the results are in the caller's host
+ * arrays.  Sizes are in elements unless stated otherwise.
+ */
+#ifndef LINGAM_H
+#define LINGAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lingam_status {
+  LINGAM_OK = 0,
+  LINGAM_E_INVALID = 1,     /* bad argument: null pointer, n < 2, p < 1, size overflow,
+                               wrong struct_size, forced order not a prefix of a permutation */
+  LINGAM_E_NONFINITE = 2,   /* NaN or Inf in X (result.bad_i = variable) */
+  LINGAM_E_DEGENERATE = 3,  /* a row of zero variance (bad_i), or an evaluated pair with
+                               1 - corr^2 <= 1e-12 (bad_i, bad_j): the residual cannot be
+                               normalised */
+  LINGAM_E_NOMEM = 4,       /* device allocation failed or the caller's workspace is too small */
+  LINGAM_E_DEVICE = 5,      /* HIP runtime error; lingam_last_error() holds the text */
+  LINGAM_E_UNSUPPORTED = 6  /* option combination not supported */
+} lingam_status;
+
+/* Arithmetic of the per-sample entropy reductions (the hot path).
+ *   FP64 : everything in binary64.
+ *   MIXED: the per-sample log cosh / exp terms in binary32 on the hardware
+ *          exp2/log2 units, summed in binary32 over at most 32 samples per lane
+ *          and then in binary64; residuals are formed in binary64 and then
+ *          rounded; normalisation, covariance, regression coefficients,
+ *          rank-1 updates and score sums stay binary64. */
+typedef enum lingam_precision { LINGAM_PREC_FP64 = 0, LINGAM_PREC_MIXED = 1 } lingam_precision;
+
+/* Layout of X.  VAR_MAJOR is the paper's p x n matrix, row i = the n samples
+ * of variable i (Alg. 1 input).  SAMPLE_MAJOR is n x p, row k = sample k. */
+typedef enum lingam_layout { LINGAM_LAYOUT_VAR_MAJOR = 0, LINGAM_LAYOUT_SAMPLE_MAJOR = 1 } lingam_layout;
+
+typedef struct lingam_opts {
+  uint32_t struct_size;        /* must be sizeof(lingam_opts) */
+  int32_t precision;           /* lingam_precision, default FP64 */
+  int32_t layout;              /* lingam_layout, default VAR_MAJOR */
+  int32_t x_dtype;             /* 0 = double, 1 = float; default 0 */
+  int32_t x_on_device;         /* 1 = X is a device pointer on `device`, 0 = host pointer */
+  int32_t device;              /* HIP device ordinal; -1 = the current device */
+  int32_t use_threshold;       /* 1 = threshold early exit (default), 0 = evaluate every pair */
+  double gamma0;               /* initial threshold per iteration; <= 0 selects 1e-6 */
+  double gamma_mult;           /* threshold multiplier c; <= 1 selects 4 */
+  int32_t cov_refresh_every;   /* k > 0: recompute the correlation matrix from the updated data
+                                  every k iterations (FP64 matrix cores); 0 = only the rank-1
+                                  UpdateCovMat recursion; default 1 */
+  int32_t max_roots;           /* 0 = full order; m > 0 = stop after m roots */
+  const int32_t* forced_order; /* optional host array: follow these roots for the first
+                                  forced_len iterations (scores are still computed) */
+  int32_t forced_len;
+  int32_t record_M_iters;      /* record the full test matrix for the first k iterations */
+  int32_t band_tiles;          /* tuning: tiles per threshold band, 0 = automatic */
+  int32_t chunk_samples;       /* tuning: samples per work-group chunk (multiple of 256), 0 = auto */
+  void* stream;                /* hipStream_t to run on; NULL = a library-owned stream */
+} lingam_opts;
+
+/* Outputs.  All arrays are host memory owned by the caller; NULL = not wanted. */
+typedef struct lingam_result {
+  int32_t* order;       /* [p], required: order[t] = original index of the t-th root;
+                           -1 past the last root produced */
+  double* T;            /* [p*p]: T[t*p + v] = -S_v at iteration t (NaN if v not in U_t) */
+  uint8_t* T_state;     /* [p*p]: 0 = v not in U_t, 1 = complete score, 2 = pruned by the
+                           threshold (partial score: T is an upper bound of the full one) */
+  double* H;            /* [p*p]: H[t*p + v] = entropy estimate of variable v at iteration t */
+  double* M;            /* [record_M_iters*p*p]: M[t*p*p + i*p + j] = I(x_i, x_j, ...) at
+                           iteration t; NaN where not evaluated */
+  uint64_t pairs_evaluated;   /* unordered pairs whose test was needed and evaluated */
+  uint64_t pair_samples;      /* pairs_evaluated x n (the throughput unit) */
+  uint64_t pairs_computed;    /* pairs actually run by the kernel (>= pairs_evaluated) */
+  uint64_t threshold_rounds;  /* threshold rounds over all iterations */
+  uint64_t bands;             /* band launches over all iterations */
+  double seconds_total;       /* wall time of the call */
+  double seconds_device;      /* device time from the first to the last kernel */
+  int32_t iterations;         /* scored iterations run */
+  int32_t bad_i, bad_j;       /* diagnostics for NONFINITE / DEGENERATE, else -1 */
+} lingam_result;
+
+/* Fill *o with the defaults listed above (struct_size set). */
+void lingam_opts_default(lingam_opts* o);
+
+/*
+ * Causal order of the p variables of X (n samples each).
+ *   X   : p x n (VAR_MAJOR) or n x p (SAMPLE_MAJOR) array of x_dtype, host or
+ *         device memory per opts->x_on_device; read only, not retained.
+ *   o   : options, NULL = defaults.
+ *   out : results (out->order required).
+ * Returns LINGAM_OK or an error status; on error the order holds the roots
+ * found so far.  Concurrent calls on different streams are allowed.
+ */
+lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam_opts* o,
+                               lingam_result* out);
+
+/* One data set of a batch: either its own X (sample_idx == NULL), or a
+ * bootstrap resample of X given as n_idx sample indices (with repetitions)
+ * into the n columns of X. */
+typedef struct lingam_dataset {
+  const void* X;
+  int64_t n, p;
+  const int64_t* sample_idx; /* host array of n_idx indices in [0, n), or NULL */
+  int64_t n_idx;
+} lingam_dataset;
+
+/* Causal orders of `count` independent data sets in one persistent launch
+ * per iteration step.  outs[k] receives the result of sets[k]; the options
+ * apply to every set (forced_order and record_M_iters must be unset). */
+lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets,
+                                     const lingam_opts* o, lingam_result* outs);
+
+/* Device bytes the library allocates for one call of lingam_fit_order. */
+uint64_t lingam_workspace_size(int64_t n, int64_t p, const lingam_opts* o);
+
+/* Static text for a status code. */
+const char* lingam_status_string(lingam_status s);
+
+/* Detail text of the last error raised on the calling thread ("" if none). */
+const char* lingam_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LINGAM_H */

@@ -46,9 +46,9 @@ def _load():
     lib.oracle_compare.restype = ctypes.c_int
     lib.oracle_compare.argtypes = [dp, dp, i64, dp]
     lib.oracle_fit_order.restype = ctypes.c_int
-    lib.oracle_fit_order.argtypes = [dp, i64, i64, i32, ip, i32, i32, ip, dp, dp, i32, ip, ip]
+    lib.oracle_fit_order.argtypes = [dp, i64, i64, i32, ip, i32, i32, ip, dp, dp, dp, dp, i32, ip, ip]
     lib.oracle_sampled_at.restype = ctypes.c_int
-    lib.oracle_sampled_at.argtypes = [dp, i64, i64, ip, i32, ip, i32, dp, ip, ip, i32, dp, i32]
+    lib.oracle_sampled_at.argtypes = [dp, i64, i64, ip, i32, ip, i32, dp, ip, ip, i32, dp, dp, i32]
     _lib = lib
     return lib
 
@@ -104,29 +104,36 @@ def fit_order(X, max_roots=0, forced_order=None, nthreads=0, M_iters=0, want_T=T
     """Plain DirectLiNGAM causal-order search (Alg. 1 lines 1-7, Alg. 2).
 
     Returns dict(order=int32[p] (-1 past the last root), T=float64[p,p] or None
-    (T[t, v] = -S_v at iteration t, NaN if v is not in U_t), M=float64[M_iters,p,p]
-    or None).  Raises OracleError on invalid/degenerate input.
+    (T[t, v] = -S_v at iteration t, NaN if v is not in U_t), H=float64[p,p] or None
+    (H[t, v] = entropy estimate of normalised x_v at iteration t),
+    M=float64[M_iters,p,p] or None, B=float64[M_iters,p,p] or None: the correlation of
+    each normalised pair, i.e. its regression coefficient).  Raises OracleError on
+    invalid/degenerate input.
     """
     X = _f64(X)
     p, n = X.shape
     order = np.full(p, -1, dtype=np.int32)
     T = np.full((p, p), np.nan) if want_T else None
+    H = np.full((p, p), np.nan) if want_T else None
     M = np.full((M_iters, p, p), np.nan) if M_iters > 0 else None
+    B = np.full((M_iters, p, p), np.nan) if M_iters > 0 else None
     fo = np.ascontiguousarray(forced_order if forced_order is not None else [], dtype=np.int32)
     bi, bj = ctypes.c_int32(-1), ctypes.c_int32(-1)
     st = _load().oracle_fit_order(
         _dp(X), n, p, int(max_roots), _ip(fo) if fo.size else None, int(fo.size), int(nthreads),
-        _ip(order), _dp(T) if T is not None else None, _dp(M) if M is not None else None,
+        _ip(order), _dp(T) if T is not None else None, _dp(H) if H is not None else None,
+        _dp(M) if M is not None else None, _dp(B) if B is not None else None,
         int(M_iters), ctypes.byref(bi), ctypes.byref(bj))
     if st != OK:
         raise OracleError(st, bi.value, bj.value)
-    return {"order": order, "T": T, "M": M}
+    return {"order": order, "T": T, "H": H, "M": M, "B": B}
 
 
-def sampled_at(X, prefix, t, vars=(), pairs=(), nthreads=0):
+def sampled_at(X, prefix, t, vars=(), pairs=(), nthreads=0, with_corr=False):
     """Scores and tests at iteration t after following the root prefix[:t].
 
-    Returns (T for each v in vars, I for each ordered pair in pairs).
+    Returns (T for each v in vars, I for each ordered pair in pairs); with
+    with_corr=True also the correlation of each pair.
     """
     X = _f64(X)
     p, n = X.shape
@@ -136,10 +143,11 @@ def sampled_at(X, prefix, t, vars=(), pairs=(), nthreads=0):
     pi, pj = np.ascontiguousarray(pr[:, 0]), np.ascontiguousarray(pr[:, 1])
     T = np.full(va.size, np.nan)
     M = np.full(pi.size, np.nan)
+    Bc = np.full(pi.size, np.nan)
     st = _load().oracle_sampled_at(
         _dp(X), n, p, _ip(pre) if pre.size else None, int(t), _ip(va) if va.size else None,
         int(va.size), _dp(T), _ip(pi) if pi.size else None, _ip(pj) if pj.size else None,
-        int(pi.size), _dp(M), int(nthreads))
+        int(pi.size), _dp(M), _dp(Bc), int(nthreads))
     if st != OK:
         raise OracleError(st)
-    return T, M
+    return (T, M, Bc) if with_corr else (T, M)

@@ -158,10 +158,11 @@ static double residual_entropy(const double* a, const double* b, int64_t n,
  * ordered pair of already-normalised rows zi, zj with entropies hi, hj.
  * scratch holds 2n doubles. */
 static int compare_normalized(const double* zi, const double* zj, double hi, double hj,
-                              int64_t n, double* scratch, double* I_out) {
+                              int64_t n, double* scratch, double* I_out, double* corr_out) {
   double* tmp = scratch;
   double* r = scratch + n;
   int st;
+  if (corr_out) *corr_out = cov_of(zi, zj, n) / sqrt(cov_of(zi, zi, n) * cov_of(zj, zj, n));
   double h_ri = residual_entropy(zi, zj, n, tmp, r, &st); /* r_i^(j) */
   if (st != OR_OK) return st;
   double h_rj = residual_entropy(zj, zi, n, tmp, r, &st); /* r_j^(i) */
@@ -181,7 +182,7 @@ int oracle_compare(const double* xi, const double* xj, int64_t n, double* I_out)
   if (st == OR_OK) st = normalize_row(xj, n, zj, 0.0);
   if (st == OR_OK) {
     double hi = oracle_entropy(zi, n), hj = oracle_entropy(zj, n);
-    st = compare_normalized(zi, zj, hi, hj, n, buf + 2 * n, I_out);
+    st = compare_normalized(zi, zj, hi, hj, n, buf + 2 * n, I_out, NULL);
   }
   free(buf);
   return st;
@@ -193,12 +194,13 @@ int oracle_compare(const double* xi, const double* xj, int64_t n, double* I_out)
  *   S    : [r] out, scores (sum over j of min(0, I_ij)^2, ascending j)
  *   Mrow : optional, r x r out, Mrow[a*r+b] = I for the ordered pair (U[a], U[b]),
  *          NaN on the diagonal
+ *   Brow : optional, r x r out, correlation of the normalised pair (NaN diagonal)
  *   only : optional [r] mask; when given, only rows with only[a] != 0 get
  *          scores (other S entries are NaN) -- used by sampled checks.
  * On a degenerate pair, bad_a and bad_b receive the positions in U. */
 static int find_root_scores(const double* Z, int64_t n, const int32_t* U, int32_t r,
-                            const double* H, double* S, double* Mrow, const uint8_t* only,
-                            int nthreads, int32_t* bad_a, int32_t* bad_b) {
+                            const double* H, double* S, double* Mrow, double* Brow,
+                            const uint8_t* only, int nthreads, int32_t* bad_a, int32_t* bad_b) {
   int status = OR_OK;
   int32_t ba = -1, bb = -1;
 #ifdef _OPENMP
@@ -223,11 +225,12 @@ static int find_root_scores(const double* Z, int64_t n, const int32_t* U, int32_
       csum s = {0, 0};
       int local = OR_OK;
       if (Mrow) Mrow[(int64_t)a * r + a] = NAN;
+      if (Brow) Brow[(int64_t)a * r + a] = NAN;
       for (int32_t b = 0; b < r; ++b) {
         if (b == a) continue;
         const double* zj = Z + (int64_t)U[b] * n;
-        double I;
-        int st = compare_normalized(zi, zj, H[a], H[b], n, scratch, &I);
+        double I, corr;
+        int st = compare_normalized(zi, zj, H[a], H[b], n, scratch, &I, Brow ? &corr : NULL);
         if (st != OR_OK) {
           local = st;
 #ifdef _OPENMP
@@ -239,6 +242,7 @@ static int find_root_scores(const double* Z, int64_t n, const int32_t* U, int32_
           break;
         }
         if (Mrow) Mrow[(int64_t)a * r + b] = I;
+        if (Brow) Brow[(int64_t)a * r + b] = corr;
         double m = I < 0.0 ? I : 0.0;
         cs_add(&s, m * m);
       }
@@ -297,22 +301,28 @@ static void regress_root(double* X, const double* Z, int64_t n, const int32_t* U
  *               entries past the last root found are -1
  *   T         : optional [p*p] out, T[t*p + v] = -S_v at iteration t,
  *               NaN if v is not in U at t (or t was not run)
+ *   Hout      : optional [p*p] out, Hout[t*p + v] = H(x_v) of the normalised
+ *               variable v at iteration t (NaN if not computed)
  *   M         : optional [M_iters*p*p] out, M[t*p*p + i*p + j] = I for the
  *               ordered pair (i, j) at iteration t, NaN where undefined
+ *   Bout      : optional [M_iters*p*p] out, correlation of the normalised pair
+ *               (i, j) at iteration t (the regression coefficient), NaN where undefined
  *   bad_i/j   : variables of a degenerate or non-finite input
  * Returns OR_OK or an error status.
  */
 int oracle_fit_order(const double* X, int64_t n, int64_t p, int32_t max_roots,
                      const int32_t* forced, int32_t forced_len, int32_t nthreads,
-                     int32_t* order, double* T, double* M, int32_t M_iters,
-                     int32_t* bad_i, int32_t* bad_j) {
+                     int32_t* order, double* T, double* Hout, double* M, double* Bout,
+                     int32_t M_iters, int32_t* bad_i, int32_t* bad_j) {
   if (!X || !order || n < 2 || p < 1) return OR_E_INVALID;
   if (forced_len < 0 || (forced_len > 0 && !forced)) return OR_E_INVALID;
   if (bad_i) *bad_i = -1;
   if (bad_j) *bad_j = -1;
   for (int64_t t = 0; t < p; ++t) order[t] = -1;
   if (T) for (int64_t k = 0; k < p * p; ++k) T[k] = NAN;
+  if (Hout) for (int64_t k = 0; k < p * p; ++k) Hout[k] = NAN;
   if (M) for (int64_t k = 0; k < (int64_t)M_iters * p * p; ++k) M[k] = NAN;
+  if (Bout) for (int64_t k = 0; k < (int64_t)M_iters * p * p; ++k) Bout[k] = NAN;
   for (int64_t k = 0; k < p * n; ++k)
     if (!isfinite(X[k])) {
       if (bad_i) *bad_i = (int32_t)(k / n);
@@ -326,9 +336,10 @@ int oracle_fit_order(const double* X, int64_t n, int64_t p, int32_t max_roots,
   double* H = (double*)malloc(sizeof(double) * (size_t)p);
   double* S = (double*)malloc(sizeof(double) * (size_t)p);
   double* Mr = M ? (double*)malloc(sizeof(double) * (size_t)p * (size_t)p) : NULL;
+  double* Br = Bout ? (double*)malloc(sizeof(double) * (size_t)p * (size_t)p) : NULL;
   uint8_t* used = (uint8_t*)calloc((size_t)p, 1);
-  if (!W || !Z || !U || !H || !S || !used || (M && !Mr)) {
-    free(W); free(Z); free(U); free(H); free(S); free(Mr); free(used);
+  if (!W || !Z || !U || !H || !S || !used || (M && !Mr) || (Bout && !Br)) {
+    free(W); free(Z); free(U); free(H); free(S); free(Mr); free(Br); free(used);
     return OR_E_NOMEM;
   }
   memcpy(W, X, sizeof(double) * pn);
@@ -350,17 +361,25 @@ int oracle_fit_order(const double* X, int64_t n, int64_t p, int32_t max_roots,
       status = normalize_and_entropy(W, Z, n, U, r, H, &bad);
       if (status != OR_OK) { if (bad_i) *bad_i = bad; break; }
       int32_t ba = -1, bb = -1;
-      status = find_root_scores(Z, n, U, r, H, S, Mr, NULL, nthreads, &ba, &bb);
+      const int rec = t < M_iters;
+      status = find_root_scores(Z, n, U, r, H, S, rec ? Mr : NULL, rec ? Br : NULL, NULL,
+                                nthreads, &ba, &bb);
       if (status != OR_OK) {
         if (bad_i) *bad_i = ba >= 0 ? U[ba] : -1;
         if (bad_j) *bad_j = bb >= 0 ? U[bb] : -1;
         break;
       }
       if (T) for (int32_t a = 0; a < r; ++a) T[(int64_t)t * p + U[a]] = -S[a];
+      if (Hout) for (int32_t a = 0; a < r; ++a) Hout[(int64_t)t * p + U[a]] = H[a];
       if (M && t < M_iters) {
         for (int32_t a = 0; a < r; ++a)
           for (int32_t b = 0; b < r; ++b)
             M[(int64_t)t * p * p + (int64_t)U[a] * p + U[b]] = Mr[(int64_t)a * r + b];
+      }
+      if (Bout && t < M_iters) {
+        for (int32_t a = 0; a < r; ++a)
+          for (int32_t b = 0; b < r; ++b)
+            Bout[(int64_t)t * p * p + (int64_t)U[a] * p + U[b]] = Br[(int64_t)a * r + b];
       }
       if (forced && t < forced_len) {
         root = -1;
@@ -380,7 +399,7 @@ int oracle_fit_order(const double* X, int64_t n, int64_t p, int32_t max_roots,
     ++t;
     if (r > 0 && t < limit) regress_root(W, Z, n, U, r, root_var);  /* line 7 */
   }
-  free(W); free(Z); free(U); free(H); free(S); free(Mr); free(used);
+  free(W); free(Z); free(U); free(H); free(S); free(Mr); free(Br); free(used);
   return status;
 }
 
@@ -390,12 +409,13 @@ int oracle_fit_order(const double* X, int64_t n, int64_t p, int32_t max_roots,
  * each), then, at iteration t, returns
  *   T_out[k]  = -S_v for v = vars[k]   (k < nvars; needs all r-1 tests of v)
  *   M_out[k]  = I for the ordered pair (pi[k], pj[k])   (k < npairs)
+ *   B_out[k]  = correlation of that normalised pair (optional)
  * Variables must still be in U at iteration t.
  */
 int oracle_sampled_at(const double* X, int64_t n, int64_t p, const int32_t* prefix, int32_t t,
                       const int32_t* vars, int32_t nvars, double* T_out,
                       const int32_t* pi, const int32_t* pj, int32_t npairs, double* M_out,
-                      int32_t nthreads) {
+                      double* B_out, int32_t nthreads) {
   if (!X || n < 2 || p < 1 || t < 0 || t >= p || (t > 0 && !prefix)) return OR_E_INVALID;
   size_t pn = (size_t)p * (size_t)n;
   double* W = (double*)malloc(sizeof(double) * pn);
@@ -438,7 +458,7 @@ int oracle_sampled_at(const double* X, int64_t n, int64_t p, const int32_t* pref
         status = OR_E_INVALID;
   }
   if (status == OR_OK && nvars > 0) {
-    status = find_root_scores(Z, n, U, r, H, S, NULL, only, nthreads, NULL, NULL);
+    status = find_root_scores(Z, n, U, r, H, S, NULL, NULL, only, nthreads, NULL, NULL);
     if (status == OR_OK)
       for (int32_t k = 0; k < nvars; ++k) T_out[k] = -S[pos[vars[k]]];
   }
@@ -454,12 +474,13 @@ int oracle_sampled_at(const double* X, int64_t n, int64_t p, const int32_t* pref
 #endif
       for (int32_t k = 0; k < npairs; ++k) {
         int32_t a = pos[pi[k]], b = pos[pj[k]];
-        double I = NAN;
+        double I = NAN, corr = NAN;
         if (scratch &&
             compare_normalized(Z + (int64_t)U[a] * n, Z + (int64_t)U[b] * n, H[a], H[b], n,
-                               scratch, &I) != OR_OK)
+                               scratch, &I, &corr) != OR_OK)
           I = NAN;
         M_out[k] = I;
+        if (B_out) B_out[k] = corr;
       }
       free(scratch);
     }

@@ -1,0 +1,243 @@
+"""MI355X (gfx950) DirectLiNGAM causal-order search.
+
+Thin ctypes binding over the C ABI declared in include/lingam.h; every step of
+the search runs in the HIP library liblingam.so.  This module only marshals
+arguments.  There is no CPU fallback: if the library is not built, calls
+raise RuntimeError.
+
+    from paper_2109_13993_amd import fit_order
+    res = fit_order(X)            # X: p x n numpy array or torch tensor (row = variable)
+    res.order                     # causal order, roots first
+"""
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblingam.so")
+
+OK, E_INVALID, E_NONFINITE, E_DEGENERATE, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(7)
+PREC = {"fp64": 0, "mixed": 1, "fp32": 1}
+LAYOUT = {"var_major": 0, "sample_major": 1}
+
+# Exported symbols of the C ABI (kept in sync with include/lingam.h).
+SYMBOLS = ("lingam_opts_default", "lingam_fit_order", "lingam_fit_order_batch",
+           "lingam_workspace_size", "lingam_status_string", "lingam_last_error")
+
+
+class LingamOpts(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("precision", ctypes.c_int32),
+        ("layout", ctypes.c_int32),
+        ("x_dtype", ctypes.c_int32),
+        ("x_on_device", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("use_threshold", ctypes.c_int32),
+        ("gamma0", ctypes.c_double),
+        ("gamma_mult", ctypes.c_double),
+        ("cov_refresh_every", ctypes.c_int32),
+        ("max_roots", ctypes.c_int32),
+        ("forced_order", ctypes.POINTER(ctypes.c_int32)),
+        ("forced_len", ctypes.c_int32),
+        ("record_M_iters", ctypes.c_int32),
+        ("band_tiles", ctypes.c_int32),
+        ("chunk_samples", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class LingamResult(ctypes.Structure):
+    _fields_ = [
+        ("order", ctypes.POINTER(ctypes.c_int32)),
+        ("T", ctypes.POINTER(ctypes.c_double)),
+        ("T_state", ctypes.POINTER(ctypes.c_uint8)),
+        ("H", ctypes.POINTER(ctypes.c_double)),
+        ("M", ctypes.POINTER(ctypes.c_double)),
+        ("pairs_evaluated", ctypes.c_uint64),
+        ("pair_samples", ctypes.c_uint64),
+        ("pairs_computed", ctypes.c_uint64),
+        ("threshold_rounds", ctypes.c_uint64),
+        ("bands", ctypes.c_uint64),
+        ("seconds_total", ctypes.c_double),
+        ("seconds_device", ctypes.c_double),
+        ("iterations", ctypes.c_int32),
+        ("bad_i", ctypes.c_int32),
+        ("bad_j", ctypes.c_int32),
+    ]
+
+
+class LingamDataset(ctypes.Structure):
+    _fields_ = [
+        ("X", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("p", ctypes.c_int64),
+        ("sample_idx", ctypes.POINTER(ctypes.c_int64)),
+        ("n_idx", ctypes.c_int64),
+    ]
+
+
+class LingamError(RuntimeError):
+    def __init__(self, status, message, bad_i=-1, bad_j=-1):
+        super().__init__("lingam status %d: %s" % (status, message))
+        self.status, self.bad_i, self.bad_j = status, bad_i, bad_j
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblingam.so (raises RuntimeError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("liblingam.so not found at %s; build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'` or "
+                           "`python paper_2109_13993_amd/build.py`" % path)
+    lib = ctypes.CDLL(path)
+    lib.lingam_opts_default.restype = None
+    lib.lingam_opts_default.argtypes = [ctypes.POINTER(LingamOpts)]
+    lib.lingam_fit_order.restype = ctypes.c_int
+    lib.lingam_fit_order.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                     ctypes.POINTER(LingamOpts), ctypes.POINTER(LingamResult)]
+    lib.lingam_fit_order_batch.restype = ctypes.c_int
+    lib.lingam_fit_order_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(LingamDataset),
+                                           ctypes.POINTER(LingamOpts), ctypes.POINTER(LingamResult)]
+    lib.lingam_workspace_size.restype = ctypes.c_uint64
+    lib.lingam_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(LingamOpts)]
+    lib.lingam_status_string.restype = ctypes.c_char_p
+    lib.lingam_status_string.argtypes = [ctypes.c_int]
+    lib.lingam_last_error.restype = ctypes.c_char_p
+    lib.lingam_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+@dataclass
+class FitResult:
+    order: np.ndarray                 # [p] int32, -1 past the last root
+    T: Optional[np.ndarray] = None    # [p, p] float64, T[t, v] = -S_v at iteration t
+    T_state: Optional[np.ndarray] = None  # [p, p] uint8 (0 absent, 1 complete, 2 pruned)
+    H: Optional[np.ndarray] = None    # [p, p] entropy of v at iteration t
+    M: Optional[np.ndarray] = None    # [k, p, p] test matrices of the first k iterations
+    pairs_evaluated: int = 0
+    pair_samples: int = 0
+    pairs_computed: int = 0
+    threshold_rounds: int = 0
+    bands: int = 0
+    seconds_total: float = 0.0
+    seconds_device: float = 0.0
+    iterations: int = 0
+    extra: dict = field(default_factory=dict)
+
+
+def default_opts() -> LingamOpts:
+    o = LingamOpts()
+    load_library().lingam_opts_default(ctypes.byref(o))
+    return o
+
+
+def _make_opts(precision="fp64", use_threshold=True, gamma0=0.0, gamma_mult=0.0,
+               cov_refresh_every=None, max_roots=0, forced_order=None, record_M_iters=0,
+               band_tiles=0, chunk_samples=0, layout="var_major", device=-1):
+    o = default_opts()
+    o.precision = PREC[precision]
+    o.layout = LAYOUT[layout]
+    o.use_threshold = 1 if use_threshold else 0
+    o.gamma0 = float(gamma0)
+    o.gamma_mult = float(gamma_mult)
+    if cov_refresh_every is not None:
+        o.cov_refresh_every = int(cov_refresh_every)
+    o.max_roots = int(max_roots)
+    o.record_M_iters = int(record_M_iters)
+    o.band_tiles = int(band_tiles)
+    o.chunk_samples = int(chunk_samples)
+    o.device = int(device)
+    keep = None
+    if forced_order is not None and len(forced_order) > 0:
+        keep = np.ascontiguousarray(forced_order, dtype=np.int32)
+        o.forced_order = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        o.forced_len = keep.size
+    return o, keep
+
+
+def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: float = 0.0,
+              gamma_mult: float = 0.0, cov_refresh_every=None, max_roots: int = 0,
+              forced_order=None, record_M_iters: int = 0, want_T: bool = True,
+              want_H: bool = True, band_tiles: int = 0, chunk_samples: int = 0,
+              layout: str = "var_major", stream=None) -> FitResult:
+    """Causal order of the variables of X (lingam_fit_order).
+
+    X is a p x n array (row i = samples of variable i; layout="sample_major"
+    for n x p) of float64 or float32: a numpy array (copied to the device by the
+    library) or a torch tensor (a CUDA/HIP tensor is used in place on its
+    device and on `stream`, default the current torch stream).
+    """
+    lib = load_library()
+    o, keep = _make_opts(precision, use_threshold, gamma0, gamma_mult, cov_refresh_every,
+                         max_roots, forced_order, record_M_iters, band_tiles, chunk_samples, layout)
+    is_torch = type(X).__module__.startswith("torch")
+    if is_torch:
+        import torch
+        if X.dtype not in (torch.float64, torch.float32):
+            raise TypeError("X must be float64 or float32")
+        X = X.contiguous()
+        ptr = X.data_ptr()
+        o.x_dtype = 0 if X.dtype == torch.float64 else 1
+        if X.is_cuda:
+            o.x_on_device = 1
+            o.device = X.device.index if X.device.index is not None else torch.cuda.current_device()
+            s = stream if stream is not None else torch.cuda.current_stream(X.device)
+            o.stream = ctypes.c_void_p(s.cuda_stream if hasattr(s, "cuda_stream") else int(s))
+        shape = tuple(X.shape)
+        host_ref = X
+    else:
+        arr = np.asarray(X)
+        if arr.dtype not in (np.float64, np.float32):
+            arr = arr.astype(np.float64)
+        arr = np.ascontiguousarray(arr)
+        o.x_dtype = 0 if arr.dtype == np.float64 else 1
+        ptr = arr.ctypes.data
+        shape = arr.shape
+        host_ref = arr
+        if stream is not None:
+            o.stream = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    if len(shape) != 2:
+        raise ValueError("X must be 2-D")
+    p, n = (shape[0], shape[1]) if layout == "var_major" else (shape[1], shape[0])
+    order = np.full(p, -1, dtype=np.int32)
+    T = np.full((p, p), np.nan) if want_T else None
+    Ts = np.zeros((p, p), dtype=np.uint8) if want_T else None
+    H = np.full((p, p), np.nan) if want_H else None
+    M = np.full((record_M_iters, p, p), np.nan) if record_M_iters > 0 else None
+    res = LingamResult()
+    res.order = order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    if T is not None:
+        res.T = T.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        res.T_state = Ts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    if H is not None:
+        res.H = H.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if M is not None:
+        res.M = M.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st = lib.lingam_fit_order(ctypes.c_void_p(ptr), n, p, ctypes.byref(o), ctypes.byref(res))
+    del host_ref, keep
+    if st != OK:
+        raise LingamError(st, lib.lingam_last_error().decode(), res.bad_i, res.bad_j)
+    return FitResult(order=order, T=T, T_state=Ts, H=H, M=M,
+                     pairs_evaluated=res.pairs_evaluated, pair_samples=res.pair_samples,
+                     pairs_computed=res.pairs_computed, threshold_rounds=res.threshold_rounds,
+                     bands=res.bands, seconds_total=res.seconds_total,
+                     seconds_device=res.seconds_device, iterations=res.iterations)
+
+
+def status_string(status: int) -> str:
+    return load_library().lingam_status_string(int(status)).decode()
+
+
+def workspace_size(n: int, p: int, precision: str = "fp64") -> int:
+    o, _ = _make_opts(precision)
+    return int(load_library().lingam_workspace_size(n, p, ctypes.byref(o)))

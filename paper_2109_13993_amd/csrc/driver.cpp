@@ -1,0 +1,466 @@
+// Host runtime and C ABI of the MI355X DirectLiNGAM causal-order search.
+//
+// One call of lingam_fit_order runs Alg. 3 of ParaLiNGAM (arXiv 2109.13993)
+// on one GPU: NormalizeData and CalculateCovMat once, then for every
+// iteration the per-variable entropies, the threshold rounds of
+// ParaFindRoot (pair kernel + score kernel, Sec. 3.2-3.3 and 4.3), and the
+// UpdateData / UpdateCovMat rank-1 updates (Sec. 3.4).  Every decision of an
+// iteration (threshold, termination, root) is taken on the device, so the
+// host only queues launches; it synchronises once every SYNC_EVERY
+// iterations to check for errors and for iterations that needed more
+// threshold rounds than were queued.
+#include "lingam.h"
+#include "lingam_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace lingam;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct HipFail {
+  hipError_t err;
+  const char* what;
+  int line;
+};
+
+#define HIPCHK(x)                                         \
+  do {                                                    \
+    hipError_t e_ = (x);                                  \
+    if (e_ != hipSuccess) throw HipFail{e_, #x, __LINE__}; \
+  } while (0)
+
+// Device allocations of one call, released on every exit path.
+struct Allocs {
+  std::vector<void*> ptrs;
+  ~Allocs() {
+    for (void* q : ptrs) (void)hipFree(q);
+  }
+  template <class T>
+  T* get(size_t count) {
+    void* q = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&q, count * sizeof(T));
+    if (e != hipSuccess) throw HipFail{e, "hipMalloc", __LINE__};
+    ptrs.push_back(q);
+    return static_cast<T*>(q);
+  }
+};
+
+struct OwnedStream {
+  hipStream_t s = nullptr;
+  bool owned = false;
+  ~OwnedStream() {
+    if (owned && s) (void)hipStreamDestroy(s);
+  }
+};
+
+constexpr int SYNC_EVERY = 16;   // iterations queued between host checks
+constexpr int QUEUED_ROUNDS = 4; // threshold rounds queued per iteration
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct Plan {
+  int chunk = CHUNK_DEFAULT;
+  int nchunk = 1;
+  int band_tiles = 0;
+};
+
+Plan make_plan(int64_t n, const lingam_opts& o) {
+  Plan pl;
+  int chunk = o.chunk_samples > 0 ? o.chunk_samples : CHUNK_DEFAULT;
+  if (o.precision == LINGAM_PREC_MIXED) chunk = std::min(chunk, CHUNK_MAX_MIXED);
+  pl.chunk = chunk;
+  pl.nchunk = (int)((n + chunk - 1) / chunk);
+  pl.band_tiles = o.band_tiles > 0 ? o.band_tiles : std::max(1, 2048 / pl.nchunk);
+  return pl;
+}
+
+// Round-0 bands of an iteration with r variables: consecutive block
+// distances grouped until a band holds at least `min_tiles` oriented tiles.
+std::vector<BandArgs> round0_bands(int r, const Plan& pl, bool threshold) {
+  std::vector<BandArgs> out;
+  const int nb = (r + TB - 1) / TB;
+  const int dmax = nb / 2;
+  if (!threshold) {
+    BandArgs a{r, nb, 0, dmax + 1, 0, 0, pl.nchunk, pl.chunk};
+    for (int d = 0; d <= dmax; ++d) a.ntiles += tiles_at_distance(nb, d, 0);
+    out.push_back(a);
+    return out;
+  }
+  int d = 0;
+  while (d <= dmax) {
+    BandArgs a{r, nb, d, d, 1, 0, pl.nchunk, pl.chunk};
+    while (a.d1 <= dmax && (a.ntiles < pl.band_tiles || a.d1 == a.d0)) {
+      a.ntiles += tiles_at_distance(nb, a.d1, 1);
+      ++a.d1;
+    }
+    out.push_back(a);
+    d = a.d1;
+  }
+  return out;
+}
+
+BandArgs full_band(int r, const Plan& pl) {
+  const int nb = (r + TB - 1) / TB;
+  BandArgs a{r, nb, 0, nb / 2 + 1, 1, 0, pl.nchunk, pl.chunk};
+  for (int d = 0; d <= nb / 2; ++d) a.ntiles += tiles_at_distance(nb, d, 1);
+  return a;
+}
+
+lingam_status fail(lingam_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+lingam_status validate(const void* X, int64_t n, int64_t p, const lingam_opts& o, const lingam_result* out) {
+  if (!X) return fail(LINGAM_E_INVALID, "X is NULL");
+  if (!out || !out->order) return fail(LINGAM_E_INVALID, "result or result->order is NULL");
+  if (o.struct_size != sizeof(lingam_opts)) return fail(LINGAM_E_INVALID, "opts.struct_size mismatch");
+  if (n < 2) return fail(LINGAM_E_INVALID, "n must be >= 2");
+  if (p < 1) return fail(LINGAM_E_INVALID, "p must be >= 1");
+  if (p > 65535) return fail(LINGAM_E_INVALID, "p must be <= 65535");
+  if (n > ((int64_t)1 << 40) || p * n > ((int64_t)1 << 40)) return fail(LINGAM_E_INVALID, "p * n too large");
+  if (o.precision != LINGAM_PREC_FP64 && o.precision != LINGAM_PREC_MIXED)
+    return fail(LINGAM_E_INVALID, "unknown precision");
+  if (o.layout != LINGAM_LAYOUT_VAR_MAJOR && o.layout != LINGAM_LAYOUT_SAMPLE_MAJOR)
+    return fail(LINGAM_E_INVALID, "unknown layout");
+  if (o.x_dtype != 0 && o.x_dtype != 1) return fail(LINGAM_E_INVALID, "x_dtype must be 0 or 1");
+  if (o.max_roots < 0) return fail(LINGAM_E_INVALID, "max_roots < 0");
+  if (o.record_M_iters < 0 || o.record_M_iters > p) return fail(LINGAM_E_INVALID, "record_M_iters out of range");
+  if (o.record_M_iters > 0 && !out->M) return fail(LINGAM_E_INVALID, "record_M_iters > 0 but result->M is NULL");
+  if (o.chunk_samples < 0 || o.chunk_samples % SUB != 0)
+    return fail(LINGAM_E_INVALID, "chunk_samples must be a multiple of 256");
+  if (o.band_tiles < 0) return fail(LINGAM_E_INVALID, "band_tiles < 0");
+  if (o.forced_len < 0 || o.forced_len > p || (o.forced_len > 0 && !o.forced_order))
+    return fail(LINGAM_E_INVALID, "bad forced_order / forced_len");
+  if (o.forced_len > 0) {
+    std::vector<char> seen((size_t)p, 0);
+    for (int k = 0; k < o.forced_len; ++k) {
+      const int32_t v = o.forced_order[k];
+      if (v < 0 || v >= p || seen[(size_t)v]) return fail(LINGAM_E_INVALID, "forced_order is not a prefix of a permutation");
+      seen[(size_t)v] = 1;
+    }
+  }
+  return LINGAM_OK;
+}
+
+void reset_result(lingam_result* out, int64_t p, int rec) {
+  for (int64_t t = 0; t < p; ++t) out->order[t] = -1;
+  if (out->T) for (int64_t k = 0; k < p * p; ++k) out->T[k] = NAN;
+  if (out->T_state) std::memset(out->T_state, 0, (size_t)(p * p));
+  if (out->H) for (int64_t k = 0; k < p * p; ++k) out->H[k] = NAN;
+  if (out->M) for (int64_t k = 0; k < (int64_t)rec * p * p; ++k) out->M[k] = NAN;
+  out->pairs_evaluated = out->pair_samples = out->pairs_computed = 0;
+  out->threshold_rounds = out->bands = 0;
+  out->seconds_total = out->seconds_device = 0.0;
+  out->iterations = 0;
+  out->bad_i = out->bad_j = -1;
+}
+
+struct Fit {
+  Dev d;
+  Plan pl;
+  lingam_opts o;
+  hipStream_t s;
+  int p;
+  int64_t n;
+  bool mixed;
+  bool threshold;
+  double gamma0, gmult;
+
+  void queue_rounds(int t, int r, int buf, int nrounds) {
+    for (int rd = 0; rd < nrounds; ++rd) {
+      if (rd == 0) {
+        auto bands = round0_bands(r, pl, threshold);
+        for (size_t b = 0; b < bands.size(); ++b) {
+          HIPCHK(launch_pair_band(d, buf, bands[b], mixed, s));
+          HIPCHK(launch_score(d, buf, r, pl.nchunk, b + 1 == bands.size() ? 1 : 0, t, gmult, s));
+        }
+      } else {
+        HIPCHK(launch_pair_band(d, buf, full_band(r, pl), mixed, s));
+        HIPCHK(launch_score(d, buf, r, pl.nchunk, 1, t, gmult, s));
+      }
+    }
+  }
+
+  void queue_tail(int t, int r, int buf) {
+    HIPCHK(launch_finish_iter(d, buf, r, t, s));
+    if (t < d.rec) HIPCHK(launch_record_M(d, buf, r, t, s));
+    const bool refresh = o.cov_refresh_every > 0 && ((t + 1) % o.cov_refresh_every == 0);
+    HIPCHK(launch_update(d, buf, r, refresh ? 1 : 0, s));
+  }
+
+  void queue_iteration(int t) {
+    const int r = p - t, buf = t & 1;
+    HIPCHK(launch_entropy(d, buf, r, mixed, s));
+    HIPCHK(launch_iter_init(d, r, threshold ? gamma0 : INFINITY, s));
+    queue_rounds(t, r, buf, threshold ? QUEUED_ROUNDS : 1);
+    queue_tail(t, r, buf);
+  }
+
+  Ctl read_ctl() {
+    Ctl c;
+    HIPCHK(hipMemcpyAsync(&c, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return c;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+void lingam_opts_default(lingam_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(lingam_opts);
+  o->precision = LINGAM_PREC_FP64;
+  o->layout = LINGAM_LAYOUT_VAR_MAJOR;
+  o->x_dtype = 0;
+  o->x_on_device = 0;
+  o->device = -1;
+  o->use_threshold = 1;
+  o->gamma0 = 1e-6;
+  o->gamma_mult = 4.0;
+  o->cov_refresh_every = 1;
+  o->max_roots = 0;
+  o->forced_order = nullptr;
+  o->forced_len = 0;
+  o->record_M_iters = 0;
+  o->band_tiles = 0;
+  o->chunk_samples = 0;
+  o->stream = nullptr;
+}
+
+const char* lingam_status_string(lingam_status s) {
+  switch (s) {
+    case LINGAM_OK: return "ok";
+    case LINGAM_E_INVALID: return "invalid argument";
+    case LINGAM_E_NONFINITE: return "non-finite value in X";
+    case LINGAM_E_DEGENERATE: return "degenerate input (zero variance or collinear pair)";
+    case LINGAM_E_NOMEM: return "out of device memory";
+    case LINGAM_E_DEVICE: return "HIP device error";
+    case LINGAM_E_UNSUPPORTED: return "unsupported option combination";
+  }
+  return "unknown status";
+}
+
+const char* lingam_last_error(void) { return g_last_error.c_str(); }
+
+uint64_t lingam_workspace_size(int64_t n, int64_t p, const lingam_opts* o) {
+  lingam_opts def;
+  lingam_opts_default(&def);
+  const lingam_opts& op = o ? *o : def;
+  if (n < 2 || p < 1) return 0;
+  const Plan pl = make_plan(n, op);
+  const uint64_t ldz = (uint64_t)round_up(n, SUB);
+  const uint64_t P = (uint64_t)p, pp = P * P;
+  uint64_t b = 0;
+  b += 2 * P * ldz * 8;                 // Z
+  b += 2 * pp * 8 + 2 * P * 4;          // Sigma, idx
+  b += pp * 8 + pp;                     // M, pend
+  b += (uint64_t)pl.nchunk * pp * 32;   // partials
+  b += 4 * P * 8 + 2 * P;               // H, S, stats, alive/complete
+  b += pp * (8 + 1 + 8) + P * 4;        // T, T_state, H record, order
+  b += (uint64_t)op.record_M_iters * pp * 8;
+  if (!op.x_on_device) b += P * (uint64_t)n * (op.x_dtype == 1 ? 4 : 8);
+  b += sizeof(Ctl);
+  return b;
+}
+
+lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam_opts* opts,
+                               lingam_result* out) {
+  const auto wall0 = std::chrono::steady_clock::now();
+  g_last_error.clear();
+  lingam_opts o;
+  if (opts) o = *opts; else lingam_opts_default(&o);
+  lingam_status st = validate(X, n, p, o, out);
+  if (st != LINGAM_OK) return st;
+  reset_result(out, p, o.record_M_iters);
+
+  Allocs al;
+  OwnedStream os;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  try {
+    if (o.device >= 0) HIPCHK(hipSetDevice(o.device));
+    if (o.stream) {
+      os.s = (hipStream_t)o.stream;
+    } else {
+      HIPCHK(hipStreamCreate(&os.s));
+      os.owned = true;
+    }
+    Fit f;
+    f.o = o;
+    f.s = os.s;
+    f.p = (int)p;
+    f.n = n;
+    f.mixed = o.precision == LINGAM_PREC_MIXED;
+    f.threshold = o.use_threshold != 0;
+    f.gamma0 = o.gamma0 > 0 ? o.gamma0 : 1e-6;
+    f.gmult = o.gamma_mult > 1.0 ? o.gamma_mult : 4.0;
+    f.pl = make_plan(n, o);
+    Dev& d = f.d;
+    d.p = (int)p;
+    d.n = n;
+    d.ldz = round_up(n, SUB);
+    const size_t P = (size_t)p, pp = P * P;
+    d.Z[0] = al.get<double>(P * d.ldz);
+    d.Z[1] = al.get<double>(P * d.ldz);
+    d.Sig[0] = al.get<double>(pp);
+    d.Sig[1] = al.get<double>(pp);
+    d.dsc[0] = al.get<double>(P);
+    d.dsc[1] = al.get<double>(P);
+    d.idx[0] = al.get<int32_t>(P);
+    d.idx[1] = al.get<int32_t>(P);
+    d.H = al.get<double>(P);
+    d.M = al.get<double>(pp);
+    d.S = al.get<double>(P);
+    d.alive = al.get<uint8_t>(P);
+    d.complete = al.get<uint8_t>(P);
+    d.pend = al.get<uint8_t>(pp);
+    d.nchunk_max = f.pl.nchunk;
+    d.P = al.get<double>((size_t)f.pl.nchunk * pp * 4);
+    d.ctl = al.get<Ctl>(1);
+    d.order = al.get<int32_t>(P);
+    d.Tall = al.get<double>(pp);
+    d.Tstate = al.get<uint8_t>(pp);
+    d.Hall = al.get<double>(pp);
+    d.rec = o.record_M_iters;
+    d.Mrec = d.rec > 0 ? al.get<double>((size_t)d.rec * pp) : nullptr;
+    d.stats = al.get<double>(2 * P);
+    d.forced_len = o.forced_len;
+    int32_t* forced_dev = al.get<int32_t>(std::max<size_t>(1, (size_t)o.forced_len));
+    d.forced = forced_dev;
+
+    const void* Xd = X;
+    if (!o.x_on_device) {
+      const size_t bytes = P * (size_t)n * (o.x_dtype == 1 ? 4 : 8);
+      void* xb = al.get<uint8_t>(bytes);
+      HIPCHK(hipMemcpyAsync(xb, X, bytes, hipMemcpyHostToDevice, f.s));
+      Xd = xb;
+    }
+    if (o.forced_len > 0)
+      HIPCHK(hipMemcpyAsync(forced_dev, o.forced_order, sizeof(int32_t) * o.forced_len, hipMemcpyHostToDevice, f.s));
+    {
+      std::vector<int32_t> iota((size_t)p);
+      for (int64_t k = 0; k < p; ++k) iota[(size_t)k] = (int32_t)k;
+      HIPCHK(hipMemcpyAsync(d.idx[0], iota.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, f.s));
+      HIPCHK(hipStreamSynchronize(f.s));  // iota is a host temporary
+    }
+    Ctl c0;
+    std::memset(&c0, 0, sizeof(c0));
+    c0.halt_iter = -1;
+    c0.root = -1;
+    c0.bad_i = c0.bad_j = -1;
+    HIPCHK(hipMemcpyAsync(d.ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, f.s));
+    // fills by kernel (no memset nodes, so the sequence stays graph-capturable)
+    HIPCHK(launch_fill(d.Z[1], (int64_t)(P * d.ldz), 0.0, f.s));
+    HIPCHK(launch_fill(d.M, (int64_t)pp, NAN, f.s));
+    HIPCHK(launch_fill_u8(d.pend, (int64_t)pp, 0, f.s));
+    HIPCHK(launch_fill(d.Tall, (int64_t)pp, NAN, f.s));
+    HIPCHK(launch_fill_u8(d.Tstate, (int64_t)pp, 0, f.s));
+    HIPCHK(launch_fill(d.Hall, (int64_t)pp, NAN, f.s));
+    if (d.Mrec) HIPCHK(launch_fill(d.Mrec, (int64_t)d.rec * (int64_t)pp, NAN, f.s));
+    HIPCHK(launch_fill_u8(reinterpret_cast<uint8_t*>(d.order), (int64_t)(4 * P), 0xff, f.s));
+
+    HIPCHK(hipEventCreate(&ev0));
+    HIPCHK(hipEventCreate(&ev1));
+    HIPCHK(hipEventRecord(ev0, f.s));
+
+    // a1 + a2: normalise once, covariance once (Alg. 3)
+    HIPCHK(launch_standardize(Xd, o.x_dtype, o.layout, n, (int)p, d, f.s));
+    HIPCHK(launch_gram(d, 0, (int)p, f.s));
+
+    const int limit = (o.max_roots > 0 && o.max_roots < p) ? o.max_roots : (int)p;
+    int t = 0;  // next iteration to queue
+    Ctl c{};
+    while (t < limit) {
+      // queue up to SYNC_EVERY iterations without waiting on the device
+      for (int q = 0; q < SYNC_EVERY && t < limit; ++q, ++t) {
+        if ((int)p - t == 1) {
+          HIPCHK(launch_last(d, t & 1, t, f.s));
+        } else {
+          f.queue_iteration(t);
+        }
+      }
+      c = f.read_ctl();
+      if (c.status != ST_OK) break;
+      if (c.halt && c.halt_iter >= 0) {
+        // iteration halt_iter needed more threshold rounds than were queued;
+        // every launch queued after it returned at once, so its state is intact.
+        const int tf = c.halt_iter;
+        const int rf = (int)p - tf, buf = tf & 1;
+        HIPCHK(launch_resume(d, f.s));
+        for (int extra = 0;; ++extra) {
+          HIPCHK(launch_pair_band(d, buf, full_band(rf, f.pl), f.mixed, f.s));
+          HIPCHK(launch_score(d, buf, rf, f.pl.nchunk, 1, tf, f.gmult, f.s));
+          c = f.read_ctl();
+          if (c.status != ST_OK || c.done) break;
+          if (extra > rf + 8) throw HipFail{hipErrorUnknown, "threshold rounds did not terminate", __LINE__};
+        }
+        if (c.status != ST_OK) break;
+        f.queue_tail(tf, rf, buf);
+        t = tf + 1;
+      }
+    }
+    HIPCHK(hipEventRecord(ev1, f.s));
+    c = f.read_ctl();
+
+    // results
+    std::vector<int32_t> order((size_t)p);
+    HIPCHK(hipMemcpyAsync(order.data(), d.order, sizeof(int32_t) * P, hipMemcpyDeviceToHost, f.s));
+    if (out->T) HIPCHK(hipMemcpyAsync(out->T, d.Tall, sizeof(double) * pp, hipMemcpyDeviceToHost, f.s));
+    if (out->T_state) HIPCHK(hipMemcpyAsync(out->T_state, d.Tstate, pp, hipMemcpyDeviceToHost, f.s));
+    if (out->H) HIPCHK(hipMemcpyAsync(out->H, d.Hall, sizeof(double) * pp, hipMemcpyDeviceToHost, f.s));
+    if (out->M && d.rec > 0)
+      HIPCHK(hipMemcpyAsync(out->M, d.Mrec, sizeof(double) * pp * d.rec, hipMemcpyDeviceToHost, f.s));
+    HIPCHK(hipStreamSynchronize(f.s));
+    std::memcpy(out->order, order.data(), sizeof(int32_t) * P);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) out->seconds_device = ms * 1e-3;
+    out->pairs_evaluated = c.pairs_evaluated;
+    out->pair_samples = c.pairs_evaluated * (uint64_t)n;
+    out->pairs_computed = c.pairs_computed;
+    out->threshold_rounds = c.rounds_total;
+    out->bands = c.bands_total;
+    int it = 0;
+    for (int64_t k = 0; k < p; ++k) if (order[(size_t)k] >= 0) ++it;
+    out->iterations = it;
+    if (c.status != ST_OK) {
+      out->bad_i = c.bad_i;
+      out->bad_j = c.bad_j;
+      st = c.status == ST_NONFINITE ? LINGAM_E_NONFINITE
+           : c.status == ST_DEGENERATE ? LINGAM_E_DEGENERATE : LINGAM_E_INVALID;
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "%s (variables %d, %d)", lingam_status_string(st), c.bad_i, c.bad_j);
+      g_last_error = buf;
+    }
+  } catch (const HipFail& e) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s failed: %s (line %d)", e.what, hipGetErrorString(e.err), e.line);
+    g_last_error = buf;
+    st = e.err == hipErrorOutOfMemory ? LINGAM_E_NOMEM : LINGAM_E_DEVICE;
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  out->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+  return st;
+}
+
+lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, const lingam_opts* o,
+                                     lingam_result* outs) {
+  (void)count; (void)sets; (void)o; (void)outs;
+  g_last_error = "batched execution is not available in this build";
+  return LINGAM_E_UNSUPPORTED;
+}
+
+}  // extern "C"

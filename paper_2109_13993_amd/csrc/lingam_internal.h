@@ -1,0 +1,114 @@
+// Internal declarations shared by the HIP kernels and the host driver of the
+// MI355X DirectLiNGAM causal-order search.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lingam {
+
+// Variables per tile block.  A work-group evaluates one oriented tile (A, B):
+// wave w pairs row v = 8A + w with the 8 rows of block B.
+constexpr int TB = 8;
+constexpr int PAIR_WAVES = TB;
+constexpr int PAIR_THREADS = 64 * PAIR_WAVES;
+// Samples staged through LDS per step (16 rows x SUB doubles = 32 KiB).
+constexpr int SUB = 256;
+// Samples per work-group chunk: at most 32 per lane, so the binary32 lane
+// sums of the mixed mode never run over more than 32 terms.
+constexpr int CHUNK_DEFAULT = 2048;
+constexpr int CHUNK_MAX_MIXED = 2048;
+// Degeneracy guard on 1 - corr^2 of an evaluated pair (and row variance).
+constexpr double DEGEN_EPS = 1e-12;
+
+enum Status : int32_t { ST_OK = 0, ST_INVALID = 1, ST_NONFINITE = 2, ST_DEGENERATE = 3 };
+
+// Device-resident control block of one search.  Written only by kernels
+// (and zeroed by the host before the first launch).
+struct Ctl {
+  double gamma;         // current threshold of this iteration
+  int32_t done;         // 1 = root of the current iteration found
+  int32_t root;         // root position (index into the compacted rows)
+  int32_t halt;         // 1 = every later kernel returns at once
+  int32_t halt_iter;    // iteration that raised halt (-1 = none)
+  int32_t status;       // Status of the first error
+  int32_t bad_i, bad_j; // compacted positions (pair error) or original index (row error)
+  int32_t round;        // threshold round of the current iteration
+  uint32_t score_arrive;  // arrival counter of the score kernel (last work-group decides)
+  uint32_t pad0;
+  unsigned long long pairs_evaluated;
+  unsigned long long pairs_computed;
+  unsigned long long rounds_total;
+  unsigned long long bands_total;
+};
+
+// Device pointers and sizes of one search.
+struct Dev {
+  int p = 0;                 // number of variables
+  int64_t n = 0;             // samples
+  int64_t ldz = 0;           // row stride of Z (doubles), multiple of 64
+  double* Z[2] = {nullptr, nullptr};      // p x ldz normalised rows (ping-pong by iteration parity)
+  // Sig holds G, the covariance of the stored rows (ld = p), and dsc the row
+  // scales d_i = 1/sqrt(G_ii): the normalised rows are d_i z_i and their
+  // correlation is b_ij = G_ij d_i d_j.  Re-normalising lazily this way keeps the
+  // rank-1 recursion from amplifying rounding in the row variances.
+  double* Sig[2] = {nullptr, nullptr};
+  double* dsc[2] = {nullptr, nullptr};
+  int32_t* idx[2] = {nullptr, nullptr};   // [p] compacted position -> original index
+  double* H = nullptr;       // [p] entropy estimate per compacted row
+  double* M = nullptr;       // p x p test matrix of the iteration (NaN = not evaluated)
+  double* S = nullptr;       // [p] scores (sum of min(0, M)^2 over evaluated pairs)
+  uint8_t* alive = nullptr;  // [p] S <= gamma at the last snapshot
+  uint8_t* complete = nullptr;  // [p] every pair of the row evaluated
+  uint8_t* pend = nullptr;   // p x p: partial sums written, M not yet formed
+  double* P = nullptr;       // [nchunk_max][p][p][4] per-chunk partial sums
+  int nchunk_max = 0;
+  Ctl* ctl = nullptr;
+  int32_t* order = nullptr;  // [p]
+  double* Tall = nullptr;    // [p*p]
+  uint8_t* Tstate = nullptr; // [p*p]
+  double* Hall = nullptr;    // [p*p]
+  double* Mrec = nullptr;    // [rec*p*p]
+  int rec = 0;
+  const int32_t* forced = nullptr;  // device copy of the forced prefix
+  int forced_len = 0;
+  double* stats = nullptr;   // [2*p] per-row mean/variance of the input (diagnostics)
+};
+
+// Parameters of one band launch of the pair kernel.
+struct BandArgs {
+  int r;          // remaining variables
+  int nb;         // tile blocks, ceil(r / TB)
+  int d0, d1;     // block-distance range of the band
+  int both;       // 1 = both orientations of every block pair, 0 = canonical one only
+  int ntiles;     // oriented tiles in the band
+  int nchunk;     // sample chunks per tile
+  int chunk;      // samples per chunk
+};
+
+// ---- launch wrappers (kernels.hip) --------------------------------------
+hipError_t launch_standardize(const void* X, int x_dtype, int layout, int64_t n, int p,
+                              const Dev& d, hipStream_t s);
+hipError_t launch_gram(const Dev& d, int buf, int r, hipStream_t s);
+hipError_t launch_entropy(const Dev& d, int buf, int r, int mixed, hipStream_t s);
+hipError_t launch_iter_init(const Dev& d, int r, double gamma0, hipStream_t s);
+hipError_t launch_pair_band(const Dev& d, int buf, const BandArgs& a, int mixed, hipStream_t s);
+hipError_t launch_score(const Dev& d, int buf, int r, int nchunk, int round_end, int t,
+                        double gamma_mult, hipStream_t s);
+hipError_t launch_finish_iter(const Dev& d, int buf, int r, int t, hipStream_t s);
+hipError_t launch_record_M(const Dev& d, int buf, int r, int t, hipStream_t s);
+hipError_t launch_update(const Dev& d, int buf, int r, int refresh, hipStream_t s);
+hipError_t launch_last(const Dev& d, int buf, int t, hipStream_t s);
+hipError_t launch_resume(const Dev& d, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, int64_t count, uint8_t v, hipStream_t s);
+
+// Number of oriented tiles of block distance d (nb blocks).
+__host__ __device__ inline int tiles_at_distance(int nb, int d, int both) {
+  if (d == 0) return nb;
+  if (2 * d < nb) return both ? 2 * nb : nb;
+  if (2 * d == nb) return both ? nb : nb / 2;
+  return 0;
+}
+
+}  // namespace lingam

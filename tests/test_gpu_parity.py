@@ -1,0 +1,271 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+FP64 mode.  The stated tolerance is a relative error of 1e-9 on the scores.
+A purely relative test is ill-posed for tests near zero, and both
+implementations round, so each test I_ij may also differ by an absolute
+amount derived from FP64 arithmetic:
+  |dM_ij| <= 1e-9 |M_ij| + 1e-14 max(1, s_ij^2),   s_ij^2 = 1 / (1 - b_ij^2),
+where b_ij is the pair's correlation (from the oracle).  Derivation: an
+entropy term moves by |dH| <= 2 k1 |E1 - beta| |dE1| + 2 k2 |E2| |dE2| <= 16 |dE1|
+(|E1 - beta| <= 0.1), and the sample moment of a normalised residual
+u = s (z_i - b z_j) moves by about s^2 times the ~5 ulp rounding of b and s,
+so |dM| <~ 16 * 5 * 1.1e-16 * s^2 ~ 1e-14 s^2.  The score tolerance follows
+from S_i = sum_j min(0, M_ij)^2:
+  |dT_i| <= 1e-9 |T_i| + sum_j (2 |min(0, M_ij)| lim_ij + lim_ij^2).
+The causal order must be identical.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2109_13993_amd as lg
+from paper_2109_13993_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-9
+M_ABS = 1e-14
+H_ABS = 1e-12
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def m_limit(Mo, Bo):
+    return REL * np.abs(Mo) + M_ABS * np.maximum(1.0, 1.0 / (1.0 - Bo * Bo))
+
+
+def t_limit(To, Mo, Bo):
+    """Limits for T[t, v] given the oracle's M[t, v, :] and B[t, v, :] (NaN-safe)."""
+    lim = m_limit(Mo, Bo)
+    neg = np.abs(np.minimum(Mo, 0.0))
+    extra = np.nansum(2.0 * neg * lim + lim * lim, axis=-1)
+    return REL * np.abs(To) + extra
+
+
+def check_limit(got, exp, lim, what):
+    got, exp, lim = (np.asarray(a, dtype=float) for a in (got, exp, lim))
+    fin = np.isfinite(exp)
+    assert np.array_equal(np.isfinite(got), fin), what + ": NaN pattern differs"
+    if not fin.any():
+        return 0.0
+    err = np.abs(got[fin] - exp[fin])
+    with np.errstate(invalid="ignore", divide="ignore"):
+        ratio = np.where(err == 0.0, 0.0, err / lim[fin])
+    worst = float(np.max(ratio))
+    _log("%s: max |d| %.3e  worst d/limit %.3f" % (what, float(err.max()), worst))
+    assert worst <= 1.0, what
+    return worst
+
+
+def check_fp64(g, o, iters):
+    """Compare T, H, M of iterations [0, iters) (oracle run with M_iters >= iters)."""
+    check_limit(g.M[:iters], o["M"][:iters], m_limit(o["M"][:iters], o["B"][:iters]), "M")
+    check_limit(g.T[:iters], o["T"][:iters], t_limit(o["T"][:iters], o["M"][:iters], o["B"][:iters]), "T")
+    check_limit(g.H, o["H"], np.full(o["H"].shape, H_ABS), "H")
+
+
+def full_parity(X, M_iters=None, **kw):
+    p = X.shape[0]
+    M_iters = p if M_iters is None else M_iters
+    o = oracle.fit_order(X, M_iters=M_iters)
+    g = lg.fit_order(X, precision="fp64", use_threshold=False, record_M_iters=M_iters, **kw)
+    assert list(g.order) == list(o["order"])
+    check_fp64(g, o, M_iters)
+    return g, o
+
+
+# ---- full parity at small sizes ----------------------------------------------
+
+def test_config1_fp64_full_parity():
+    ds = synth.config_dataset(1)   # p=10, n=1000
+    full_parity(ds.X)
+
+
+@pytest.mark.parametrize("p,n,noise,seed", [(27, 3001, "laplace", 1), (17, 700, "mixed", 2),
+                                            (9, 256, "uniform", 3), (33, 4097, "power15", 4)])
+def test_ragged_fp64_full_parity(p, n, noise, seed):
+    # p not a multiple of the 8-variable tiles, n not a multiple of the 256-sample stages
+    ds = synth.lingam_dataset(p, n, 0.3, noise, rng=np.random.default_rng(seed))
+    full_parity(ds.X)
+
+
+def test_small_chunks_and_bands_fp64_parity():
+    # many sample chunks per tile and one block distance per band
+    ds = synth.lingam_dataset(40, 5000, 0.2, "laplace", rng=np.random.default_rng(7))
+    g, o = full_parity(ds.X, M_iters=3, chunk_samples=512)
+    t = lg.fit_order(ds.X, precision="fp64", chunk_samples=512, band_tiles=1)
+    assert list(t.order) == list(o["order"])
+
+
+def test_threshold_keeps_order_and_complete_scores():
+    # small bands (one block distance each) so the threshold actually prunes
+    for seed, (p, n) in enumerate([(10, 1000), (27, 3001), (60, 4000)]):
+        ds = synth.lingam_dataset(p, n, 0.3, "mixed", rng=np.random.default_rng(50 + seed))
+        off = lg.fit_order(ds.X, use_threshold=False)
+        for g0, c, bt in ((1e-6, 4.0, 1), (1e-9, 2.0, 1), (1e-3, 10.0, 1), (1e-6, 4.0, 0)):
+            on = lg.fit_order(ds.X, use_threshold=True, gamma0=g0, gamma_mult=c, band_tiles=bt)
+            assert list(on.order) == list(off.order)
+            comp = on.T_state == 1
+            pruned = on.T_state == 2
+            assert np.array_equal(on.T[comp], off.T[comp])          # same values, bitwise
+            assert np.all(on.T[pruned] >= off.T[pruned])           # partial S <= full S
+            assert np.array_equal(on.T_state > 0, off.T_state > 0)
+            assert on.pairs_evaluated <= off.pairs_evaluated
+            _log("p=%d gamma0=%g c=%g band_tiles=%d: pairs %d / %d, rounds %d, bands %d" % (
+                p, g0, c, bt, on.pairs_evaluated, off.pairs_evaluated, on.threshold_rounds, on.bands))
+            if p >= 27 and bt == 1:
+                assert on.pairs_evaluated < off.pairs_evaluated
+
+
+def test_config2_fp64_parity():
+    ds = synth.config_dataset(2)   # p=100, n=10000
+    o = oracle.fit_order(ds.X, M_iters=100)
+    g = lg.fit_order(ds.X, precision="fp64", use_threshold=False, record_M_iters=100)
+    assert list(g.order) == list(o["order"])
+    check_fp64(g, o, 100)
+    on = lg.fit_order(ds.X, precision="fp64")   # default: threshold on
+    assert list(on.order) == list(o["order"])
+    small = lg.fit_order(ds.X, precision="fp64", band_tiles=8)
+    assert list(small.order) == list(o["order"])
+    assert small.pairs_evaluated < g.pairs_evaluated
+
+
+# ---- full size (p=500, n=20000): sampled outputs --------------------------------
+
+@pytest.fixture(scope="module")
+def cfg3():
+    return synth.config_dataset(3)
+
+
+def _sampled_check(X, g, prefix, t, rest, rng, nvars, npairs, tag):
+    vars_ = sorted(rng.choice(rest, nvars, replace=False).tolist())
+    pairs = [tuple(rng.choice(rest, 2, replace=False).tolist()) for _ in range(npairs)]
+    # all tests of the sampled variables, for the score limits
+    rows = [(v, j) for v in vars_ for j in rest if j != v]
+    T, Mrow, Brow = oracle.sampled_at(X, prefix, t, vars=vars_, pairs=rows + pairs, with_corr=True)
+    k = len(rows)
+    M, B = Mrow[k:], Brow[k:]
+    Mv = np.array(Mrow[:k]).reshape(len(vars_), -1)
+    Bv = np.array(Brow[:k]).reshape(len(vars_), -1)
+    check_limit(g.T[t, vars_], T, t_limit(T, Mv, Bv), "T(t=%d) %s" % (t, tag))
+    check_limit(np.array([g.M[t, i, j] for i, j in pairs]), M, m_limit(M, B), "M(t=%d) %s" % (t, tag))
+    check_limit(np.array([g.M[t, i, j] for i, j in rows]), Mv.ravel(), m_limit(Mv.ravel(), Bv.ravel()),
+                "M rows(t=%d) %s" % (t, tag))
+
+
+def test_fullsize_sampled_fp64_iteration0(cfg3):
+    X = cfg3.X
+    p = X.shape[0]
+    g = lg.fit_order(X, precision="fp64", use_threshold=False, max_roots=1, record_M_iters=1)
+    _sampled_check(X, g, [], 0, list(range(p)), np.random.default_rng(0), 6, 32, "cfg3")
+    # antisymmetry of the whole matrix, bitwise
+    Mg = g.M[0]
+    off = ~np.eye(p, dtype=bool)
+    assert np.array_equal(Mg[off], -Mg.T[off])
+
+
+def test_fullsize_sampled_fp64_teacher_forced(cfg3):
+    X = cfg3.X
+    t = 5
+    prefix = [int(v) for v in cfg3.true_order[:t]]
+    g = lg.fit_order(X, precision="fp64", use_threshold=False, forced_order=prefix,
+                     max_roots=t + 1, record_M_iters=t + 1)
+    assert list(g.order[:t]) == prefix
+    rest = sorted(set(range(X.shape[0])) - set(prefix))
+    _sampled_check(X, g, prefix, t, rest, np.random.default_rng(1), 4, 24, "cfg3 forced")
+
+
+def test_fullsize_runs_are_deterministic_and_threshold_exact(cfg3):
+    X = cfg3.X
+    a = lg.fit_order(X, precision="mixed")
+    b = lg.fit_order(X, precision="mixed")
+    assert np.array_equal(a.order, b.order)
+    assert np.array_equal(a.T, b.T, equal_nan=True)
+    assert sorted(a.order.tolist()) == list(range(X.shape[0]))
+    off = lg.fit_order(X, precision="mixed", use_threshold=False, max_roots=10)
+    assert list(off.order[:10]) == list(a.order[:10])
+    _log("cfg3 mixed: pairs %d computed %d rounds %d bands %d, %.3f s" % (
+        a.pairs_evaluated, a.pairs_computed, a.threshold_rounds, a.bands, a.seconds_device))
+
+
+# ---- mixed precision -------------------------------------------------------------
+
+def test_mixed_teacher_forced_scores():
+    ds = synth.config_dataset(2)
+    o = oracle.fit_order(ds.X, M_iters=3)
+    g = lg.fit_order(ds.X, precision="mixed", use_threshold=False, forced_order=o["order"],
+                     record_M_iters=3)
+    dM = np.nanmax(np.abs(g.M - o["M"]))
+    fin = np.isfinite(o["T"])
+    dT = np.abs(g.T[fin] - o["T"][fin])
+    dH = np.nanmax(np.abs(g.H - o["H"]))
+    _log("mixed cfg2: max|dM| %.3e  max|dT| %.3e  max|dH| %.3e" % (dM, dT.max(), dH))
+    assert dM < 1e-5 and dH < 1e-6
+
+
+# ---- edge cases and input forms ------------------------------------------------
+
+def test_one_and_two_variables():
+    rng = np.random.default_rng(3)
+    r = lg.fit_order(rng.uniform(size=(1, 100)))
+    assert list(r.order) == [0]
+    X = rng.laplace(size=(2, 3000))
+    X[1] += 0.5 * X[0]
+    o = oracle.fit_order(X, M_iters=1)
+    g = lg.fit_order(X, record_M_iters=1)
+    assert list(g.order) == list(o["order"])
+    check_limit(g.M, o["M"], m_limit(o["M"], o["B"]), "M(p=2)")
+
+
+def test_degenerate_and_nonfinite_inputs():
+    rng = np.random.default_rng(0)
+    X = rng.uniform(size=(5, 300))
+    Y = X.copy(); Y[2] = 4.0
+    with pytest.raises(lg.LingamError) as e:
+        lg.fit_order(Y)
+    assert e.value.status == lg.E_DEGENERATE and e.value.bad_i == 2
+    Y = X.copy(); Y[4] = -3.0 * Y[1] + 2.0
+    with pytest.raises(lg.LingamError) as e:
+        lg.fit_order(Y)
+    assert e.value.status == lg.E_DEGENERATE and {e.value.bad_i, e.value.bad_j} == {1, 4}
+    Y = X.copy(); Y[3, 7] = np.inf
+    with pytest.raises(lg.LingamError) as e:
+        lg.fit_order(Y)
+    assert e.value.status == lg.E_NONFINITE and e.value.bad_i == 3
+
+
+def test_max_roots_forced_order_and_input_forms():
+    ds = synth.lingam_dataset(12, 2000, 0.3, "uniform", rng=np.random.default_rng(8))
+    o = oracle.fit_order(ds.X)
+    g = lg.fit_order(ds.X)
+    assert list(g.order) == list(o["order"])
+    part = lg.fit_order(ds.X, max_roots=4)
+    assert list(part.order[:4]) == list(o["order"][:4]) and list(part.order[4:]) == [-1] * 8
+    forced = [int(o["order"][5]), int(o["order"][2])]
+    of = oracle.fit_order(ds.X, forced_order=forced)
+    gf = lg.fit_order(ds.X, forced_order=forced)
+    assert list(gf.order) == list(of["order"])
+    # sample-major layout and binary32 input give the same order
+    gs = lg.fit_order(np.ascontiguousarray(ds.X.T), layout="sample_major")
+    assert list(gs.order) == list(o["order"])
+    X32 = ds.X.astype(np.float32)
+    o32 = oracle.fit_order(X32.astype(np.float64))
+    g32 = lg.fit_order(X32)
+    assert list(g32.order) == list(o32["order"])
+
+
+def test_device_tensor_input():
+    import torch
+    ds = synth.lingam_dataset(20, 3000, 0.3, "laplace", rng=np.random.default_rng(9))
+    o = oracle.fit_order(ds.X)
+    Xd = torch.from_numpy(ds.X).to("cuda:0")
+    g = lg.fit_order(Xd)
+    assert list(g.order) == list(o["order"])
+    s = torch.cuda.Stream()
+    g2 = lg.fit_order(Xd, stream=s)
+    assert list(g2.order) == list(o["order"])
