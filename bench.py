@@ -1,0 +1,147 @@
+#!/usr/bin/env python3
+"""Benchmark of the causal-order search on one MI355X.
+
+Workload: p = 500 variables, n = 20000 samples, random DAG with edge
+probability 0.02, weights +-U[0.5, 2], Laplace noise, rows permuted (seeded,
+synthetic).  One step = one full causal-order search (normalise, covariance,
+all p iterations of entropies + threshold rounds of the pair kernel + root
+selection + rank-1 update) on the input already resident in device memory.
+
+Reported: evaluated pair-samples per second of the mixed-precision path
+(binary32 per-sample terms) and its order wall time, the same for the FP64
+path, the pair kernel's VALU roofline fraction (pair-kernel time measured with
+HIP events on the library's stream), and the FP64 CPU oracle's rate on a
+bounded sample of the same workload.  Prints one JSON line on stdout.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+# VALU issue model of gfx950 used for the pair kernel's roofline:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-slots/s (binary32
+# FMA/add/mul, binary64 FMA and conversions issue one lane-slot each;
+# v_exp_f32 / v_log_f32 take two).  One mixed-precision pair-sample needs
+# 2 binary64 FMAs + 2 conversions (the two residuals) + 2 x 7 binary32 ops and
+# 2 x 3 transcendentals (log cosh and u exp(-u^2/2) of each residual):
+# 18 + 6 x 2 = 30 lane-slots.
+PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
+SLOTS_PER_PAIR_SAMPLE_MIXED = 2 + 2 + 2 * 7 + 6 * 2
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_runs(lg, X, precision, steps, warmup, **kw):
+    import torch
+    for _ in range(warmup):
+        lg.fit_order(X, precision=precision, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [lg.fit_order(X, precision=precision, profile=True, **kw) for _ in range(steps)]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, res
+
+
+def cpu_baseline(X, nvars):
+    import oracle
+    p, n = X.shape
+    nvars = min(nvars, p)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    oracle.sampled_at(X, [], 0, vars=list(range(nvars)), nthreads=cores)
+    dt = time.perf_counter() - t0
+    pair_samples = nvars * (p - 1) * n
+    return {"value": pair_samples / dt, "unit": "pair-samples/s", "cores": cores, "kind": "oracle",
+            "sample": "iteration-0 scores of %d of the %d variables (%d tests x %d samples, "
+                      "FP64 plain DirectLiNGAM), %.1f s" % (nvars, p, nvars * (p - 1), n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 searches (default: --steps)")
+    ap.add_argument("--cpu-vars", type=int, default=160, help="variables in the CPU-oracle sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2109_13993_amd as lg
+    from paper_2109_13993_amd import synth
+
+    ds = synth.config_dataset(3)
+    p, n = ds.X.shape
+    X = torch.from_numpy(ds.X).to("cuda:0")
+    torch.cuda.synchronize()
+    log("workload p=%d n=%d on %s" % (p, n, torch.cuda.get_device_name(0)))
+
+    t_mix, res_mix = timed_runs(lg, X, "mixed", args.steps, args.warmup)
+    pairs = res_mix[-1].pair_samples
+    value = pairs / t_mix
+    kern_s = sum(r.seconds_pair_kernel for r in res_mix) / len(res_mix)
+    launches = res_mix[-1].pair_kernel_launches
+    achieved = pairs * SLOTS_PER_PAIR_SAMPLE_MIXED / kern_s
+    log("mixed: %.1f ms/search, %.3e pair-samples/s, pair kernel %.1f ms in %d launches "
+        "(%.1f us avg), pairs %d evaluated / %d computed" % (
+            t_mix * 1e3, value, kern_s * 1e3, launches, kern_s / max(launches, 1) * 1e6,
+            res_mix[-1].pairs_evaluated, res_mix[-1].pairs_computed))
+
+    out = {
+        "metric": "pair-sample evals/s + causal-order wall time, p=500 n=20k, FP32 vs FP64",
+        "value": value,
+        "unit": "pair-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_mix * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "DirectLiNGAM causal order, p=500 n=20000, edge prob 0.02, "
+                               "Laplace noise, seeded", "p": p, "n": n, "precision": "mixed",
+                   "threshold": True},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
+                     "unit": "Tlane-slot/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": None,
+                     "kernel": "k_pair_band<mixed>", "slots_per_pair_sample": SLOTS_PER_PAIR_SAMPLE_MIXED,
+                     "pair_kernel_ms_per_step": kern_s * 1e3, "launches_per_step": launches},
+        "pairs_evaluated": res_mix[-1].pairs_evaluated,
+        "pairs_computed": res_mix[-1].pairs_computed,
+        "effective_pair_samples_per_s": (p + 1) * p * (p - 1) // 6 * n / t_mix,
+        "threshold_rounds": res_mix[-1].threshold_rounds,
+    }
+    if not args.no_fp64:
+        steps64 = args.fp64_steps if args.fp64_steps is not None else args.steps
+        t64, res64 = timed_runs(lg, X, "fp64", steps64, min(args.warmup, 1))
+        v64 = res64[-1].pair_samples / t64
+        k64 = sum(r.seconds_pair_kernel for r in res64) / len(res64)
+        same = bool(np.array_equal(res64[-1].order, res_mix[-1].order))
+        first_diff = int(np.argmax(res64[-1].order != res_mix[-1].order)) if not same else -1
+        out["fp64"] = {"value": v64, "ms_per_step": t64 * 1e3, "pair_kernel_ms_per_step": k64 * 1e3,
+                       "pairs_evaluated": res64[-1].pairs_evaluated}
+        out["speedup_fp32_vs_fp64"] = t64 / t_mix
+        out["order_fp32_equals_fp64"] = same
+        out["order_first_difference"] = first_diff
+        log("fp64: %.1f ms/search, %.3e pair-samples/s, pair kernel %.1f ms; orders equal: %s" % (
+            t64 * 1e3, v64, k64 * 1e3, same))
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(ds.X, args.cpu_vars)
+        log("cpu oracle: %.3e pair-samples/s on %d threads" % (
+            out["cpu_baseline"]["value"], out["cpu_baseline"]["cores"]))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -67,7 +67,10 @@ typedef struct lingam_opts {
   int32_t x_on_device;         /* 1 = X is a device pointer on `device`, 0 = host pointer */
   int32_t device;              /* HIP device ordinal; -1 = the current device */
   int32_t use_threshold;       /* 1 = threshold early exit (default), 0 = evaluate every pair */
-  double gamma0;               /* initial threshold per iteration; <= 0 selects 1e-6 */
+  double gamma0;               /* > 0: initial threshold of every iteration; <= 0 (default):
+                                  adaptive, 1e-6 for the first iteration and then twice the
+                                  previous iteration's root score (any value gives the same
+                                  order; it only changes how many pairs are evaluated) */
   double gamma_mult;           /* threshold multiplier c; <= 1 selects 4 */
   int32_t cov_refresh_every;   /* k > 0: recompute the correlation matrix from the updated data
                                   every k iterations (FP64 matrix cores); 0 = only the rank-1
@@ -77,9 +80,13 @@ typedef struct lingam_opts {
                                   forced_len iterations (scores are still computed) */
   int32_t forced_len;
   int32_t record_M_iters;      /* record the full test matrix for the first k iterations */
-  int32_t band_tiles;          /* tuning: tiles per threshold band, 0 = automatic */
+  int32_t band_blocks;         /* tuning: target blocks of 8 variables per threshold band
+                                  (every variable below the threshold is compared with these
+                                  targets before the threshold state is refreshed); 0 = 4 */
   int32_t chunk_samples;       /* tuning: samples per work-group chunk (multiple of 256), 0 = auto */
   void* stream;                /* hipStream_t to run on; NULL = a library-owned stream */
+  int32_t profile;             /* 1 = time every pair-kernel launch with HIP events on the
+                                  stream (fills seconds_pair_kernel / pair_kernel_launches) */
 } lingam_opts;
 
 /* Outputs.  All arrays are host memory owned by the caller; NULL = not wanted. */
@@ -99,6 +106,8 @@ typedef struct lingam_result {
   uint64_t bands;             /* band launches over all iterations */
   double seconds_total;       /* wall time of the call */
   double seconds_device;      /* device time from the first to the last kernel */
+  double seconds_pair_kernel; /* summed duration of the pair-kernel launches (opts.profile) */
+  uint64_t pair_kernel_launches;  /* pair-kernel launches (counted when opts.profile) */
   int32_t iterations;         /* scored iterations run */
   int32_t bad_i, bad_j;       /* diagnostics for NONFINITE / DEGENERATE, else -1 */
 } lingam_result;

@@ -44,9 +44,10 @@ class LingamOpts(ctypes.Structure):
         ("forced_order", ctypes.POINTER(ctypes.c_int32)),
         ("forced_len", ctypes.c_int32),
         ("record_M_iters", ctypes.c_int32),
-        ("band_tiles", ctypes.c_int32),
+        ("band_blocks", ctypes.c_int32),
         ("chunk_samples", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
+        ("profile", ctypes.c_int32),
     ]
 
 
@@ -64,6 +65,8 @@ class LingamResult(ctypes.Structure):
         ("bands", ctypes.c_uint64),
         ("seconds_total", ctypes.c_double),
         ("seconds_device", ctypes.c_double),
+        ("seconds_pair_kernel", ctypes.c_double),
+        ("pair_kernel_launches", ctypes.c_uint64),
         ("iterations", ctypes.c_int32),
         ("bad_i", ctypes.c_int32),
         ("bad_j", ctypes.c_int32),
@@ -131,6 +134,8 @@ class FitResult:
     bands: int = 0
     seconds_total: float = 0.0
     seconds_device: float = 0.0
+    seconds_pair_kernel: float = 0.0
+    pair_kernel_launches: int = 0
     iterations: int = 0
     extra: dict = field(default_factory=dict)
 
@@ -143,7 +148,7 @@ def default_opts() -> LingamOpts:
 
 def _make_opts(precision="fp64", use_threshold=True, gamma0=0.0, gamma_mult=0.0,
                cov_refresh_every=None, max_roots=0, forced_order=None, record_M_iters=0,
-               band_tiles=0, chunk_samples=0, layout="var_major", device=-1):
+               band_blocks=0, chunk_samples=0, layout="var_major", device=-1, profile=False):
     o = default_opts()
     o.precision = PREC[precision]
     o.layout = LAYOUT[layout]
@@ -154,9 +159,10 @@ def _make_opts(precision="fp64", use_threshold=True, gamma0=0.0, gamma_mult=0.0,
         o.cov_refresh_every = int(cov_refresh_every)
     o.max_roots = int(max_roots)
     o.record_M_iters = int(record_M_iters)
-    o.band_tiles = int(band_tiles)
+    o.band_blocks = int(band_blocks)
     o.chunk_samples = int(chunk_samples)
     o.device = int(device)
+    o.profile = 1 if profile else 0
     keep = None
     if forced_order is not None and len(forced_order) > 0:
         keep = np.ascontiguousarray(forced_order, dtype=np.int32)
@@ -168,8 +174,8 @@ def _make_opts(precision="fp64", use_threshold=True, gamma0=0.0, gamma_mult=0.0,
 def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: float = 0.0,
               gamma_mult: float = 0.0, cov_refresh_every=None, max_roots: int = 0,
               forced_order=None, record_M_iters: int = 0, want_T: bool = True,
-              want_H: bool = True, band_tiles: int = 0, chunk_samples: int = 0,
-              layout: str = "var_major", stream=None) -> FitResult:
+              want_H: bool = True, band_blocks: int = 0, chunk_samples: int = 0,
+              layout: str = "var_major", stream=None, profile: bool = False) -> FitResult:
     """Causal order of the variables of X (lingam_fit_order).
 
     X is a p x n array (row i = samples of variable i; layout="sample_major"
@@ -179,7 +185,8 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
     """
     lib = load_library()
     o, keep = _make_opts(precision, use_threshold, gamma0, gamma_mult, cov_refresh_every,
-                         max_roots, forced_order, record_M_iters, band_tiles, chunk_samples, layout)
+                         max_roots, forced_order, record_M_iters, band_blocks, chunk_samples, layout,
+                         profile=profile)
     is_torch = type(X).__module__.startswith("torch")
     if is_torch:
         import torch
@@ -231,7 +238,8 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
                      pairs_evaluated=res.pairs_evaluated, pair_samples=res.pair_samples,
                      pairs_computed=res.pairs_computed, threshold_rounds=res.threshold_rounds,
                      bands=res.bands, seconds_total=res.seconds_total,
-                     seconds_device=res.seconds_device, iterations=res.iterations)
+                     seconds_device=res.seconds_device, seconds_pair_kernel=res.seconds_pair_kernel,
+                     pair_kernel_launches=res.pair_kernel_launches, iterations=res.iterations)
 
 
 def status_string(status: int) -> str:

@@ -65,13 +65,16 @@ struct OwnedStream {
 
 constexpr int SYNC_EVERY = 16;   // iterations queued between host checks
 constexpr int QUEUED_ROUNDS = 4; // threshold rounds queued per iteration
+constexpr int GRAM_SLICES_MAX = 16;  // sample slices of the split Gram
+constexpr int BAND_BLOCKS_DEFAULT = 4;  // target blocks per threshold band
+constexpr double GAMMA_ADAPT = 2.0;  // adaptive gamma0 = this x previous root score
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 struct Plan {
   int chunk = CHUNK_DEFAULT;
   int nchunk = 1;
-  int band_tiles = 0;
+  int band_blocks = 4;   // target blocks (of 8 variables) per threshold band
 };
 
 Plan make_plan(int64_t n, const lingam_opts& o) {
@@ -80,40 +83,24 @@ Plan make_plan(int64_t n, const lingam_opts& o) {
   if (o.precision == LINGAM_PREC_MIXED) chunk = std::min(chunk, CHUNK_MAX_MIXED);
   pl.chunk = chunk;
   pl.nchunk = (int)((n + chunk - 1) / chunk);
-  pl.band_tiles = o.band_tiles > 0 ? o.band_tiles : std::max(1, 2048 / pl.nchunk);
+  pl.band_blocks = o.band_blocks > 0 ? o.band_blocks : BAND_BLOCKS_DEFAULT;
   return pl;
 }
 
-// Round-0 bands of an iteration with r variables: consecutive block
-// distances grouped until a band holds at least `min_tiles` oriented tiles.
+// Round-0 bands of an iteration with r variables: consecutive groups of
+// `band_blocks` target blocks.  Later rounds use one band with every block.
 std::vector<BandArgs> round0_bands(int r, const Plan& pl, bool threshold) {
   std::vector<BandArgs> out;
   const int nb = (r + TB - 1) / TB;
-  const int dmax = nb / 2;
-  if (!threshold) {
-    BandArgs a{r, nb, 0, dmax + 1, 0, 0, pl.nchunk, pl.chunk};
-    for (int d = 0; d <= dmax; ++d) a.ntiles += tiles_at_distance(nb, d, 0);
-    out.push_back(a);
-    return out;
-  }
-  int d = 0;
-  while (d <= dmax) {
-    BandArgs a{r, nb, d, d, 1, 0, pl.nchunk, pl.chunk};
-    while (a.d1 <= dmax && (a.ntiles < pl.band_tiles || a.d1 == a.d0)) {
-      a.ntiles += tiles_at_distance(nb, a.d1, 1);
-      ++a.d1;
-    }
-    out.push_back(a);
-    d = a.d1;
-  }
+  const int K = threshold ? std::max(1, pl.band_blocks) : nb;
+  for (int tb0 = 0; tb0 < nb; tb0 += K)
+    out.push_back(BandArgs{r, nb, tb0, std::min(K, nb - tb0), pl.nchunk, pl.chunk, 0});
   return out;
 }
 
 BandArgs full_band(int r, const Plan& pl) {
   const int nb = (r + TB - 1) / TB;
-  BandArgs a{r, nb, 0, nb / 2 + 1, 1, 0, pl.nchunk, pl.chunk};
-  for (int d = 0; d <= nb / 2; ++d) a.ntiles += tiles_at_distance(nb, d, 1);
-  return a;
+  return BandArgs{r, nb, 0, nb, pl.nchunk, pl.chunk, 0};
 }
 
 lingam_status fail(lingam_status st, const std::string& msg) {
@@ -139,7 +126,7 @@ lingam_status validate(const void* X, int64_t n, int64_t p, const lingam_opts& o
   if (o.record_M_iters > 0 && !out->M) return fail(LINGAM_E_INVALID, "record_M_iters > 0 but result->M is NULL");
   if (o.chunk_samples < 0 || o.chunk_samples % SUB != 0)
     return fail(LINGAM_E_INVALID, "chunk_samples must be a multiple of 256");
-  if (o.band_tiles < 0) return fail(LINGAM_E_INVALID, "band_tiles < 0");
+  if (o.band_blocks < 0) return fail(LINGAM_E_INVALID, "band_blocks < 0");
   if (o.forced_len < 0 || o.forced_len > p || (o.forced_len > 0 && !o.forced_order))
     return fail(LINGAM_E_INVALID, "bad forced_order / forced_len");
   if (o.forced_len > 0) {
@@ -161,12 +148,52 @@ void reset_result(lingam_result* out, int64_t p, int rec) {
   if (out->M) for (int64_t k = 0; k < (int64_t)rec * p * p; ++k) out->M[k] = NAN;
   out->pairs_evaluated = out->pair_samples = out->pairs_computed = 0;
   out->threshold_rounds = out->bands = 0;
-  out->seconds_total = out->seconds_device = 0.0;
+  out->seconds_total = out->seconds_device = out->seconds_pair_kernel = 0.0;
+  out->pair_kernel_launches = 0;
   out->iterations = 0;
   out->bad_i = out->bad_j = -1;
 }
 
+// Optional timing of the pair-kernel launches: an event pair around each
+// launch on the same stream, summed at the end of the call.
+struct PairTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  uint64_t launches = 0;
+  ~PairTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  hipEvent_t next() {
+    if (used == ev.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+    return ev[used++];
+  }
+  double total_seconds() {
+    double s = 0.0;
+    for (size_t k = 0; k + 1 < used; k += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) s += ms * 1e-3;
+    }
+    return s;
+  }
+};
+
 struct Fit {
+  PairTimer* timer = nullptr;
+  void pair(int buf, const BandArgs& a, bool dense = false) {
+    if (timer && timer->on) {
+      HIPCHK(hipEventRecord(timer->next(), s));
+      HIPCHK(launch_pair_band(d, buf, a, mixed, dense ? 1 : 0, s));
+      HIPCHK(hipEventRecord(timer->next(), s));
+      ++timer->launches;
+    } else {
+      HIPCHK(launch_pair_band(d, buf, a, mixed, dense ? 1 : 0, s));
+    }
+  }
   Dev d;
   Plan pl;
   lingam_opts o;
@@ -182,12 +209,12 @@ struct Fit {
       if (rd == 0) {
         auto bands = round0_bands(r, pl, threshold);
         for (size_t b = 0; b < bands.size(); ++b) {
-          HIPCHK(launch_pair_band(d, buf, bands[b], mixed, s));
-          HIPCHK(launch_score(d, buf, r, pl.nchunk, b + 1 == bands.size() ? 1 : 0, t, gmult, s));
+          pair(buf, bands[b], b == 0);  // the first band still has every variable alive
+          HIPCHK(launch_score(d, buf, bands[b], b + 1 == bands.size() ? 1 : 0, t, gmult, s));
         }
       } else {
-        HIPCHK(launch_pair_band(d, buf, full_band(r, pl), mixed, s));
-        HIPCHK(launch_score(d, buf, r, pl.nchunk, 1, t, gmult, s));
+        pair(buf, full_band(r, pl));
+        HIPCHK(launch_score(d, buf, full_band(r, pl), 1, t, gmult, s));
       }
     }
   }
@@ -202,7 +229,7 @@ struct Fit {
   void queue_iteration(int t) {
     const int r = p - t, buf = t & 1;
     HIPCHK(launch_entropy(d, buf, r, mixed, s));
-    HIPCHK(launch_iter_init(d, r, threshold ? gamma0 : INFINITY, s));
+    HIPCHK(launch_iter_init(d, r, threshold ? gamma0 : INFINITY, GAMMA_ADAPT, s));
     queue_rounds(t, r, buf, threshold ? QUEUED_ROUNDS : 1);
     queue_tail(t, r, buf);
   }
@@ -229,16 +256,17 @@ void lingam_opts_default(lingam_opts* o) {
   o->x_on_device = 0;
   o->device = -1;
   o->use_threshold = 1;
-  o->gamma0 = 1e-6;
+  o->gamma0 = 0.0;
   o->gamma_mult = 4.0;
   o->cov_refresh_every = 1;
   o->max_roots = 0;
   o->forced_order = nullptr;
   o->forced_len = 0;
   o->record_M_iters = 0;
-  o->band_tiles = 0;
+  o->band_blocks = 0;
   o->chunk_samples = 0;
   o->stream = nullptr;
+  o->profile = 0;
 }
 
 const char* lingam_status_string(lingam_status s) {
@@ -270,6 +298,7 @@ uint64_t lingam_workspace_size(int64_t n, int64_t p, const lingam_opts* o) {
   b += pp * 8 + pp;                     // M, pend
   b += (uint64_t)pl.nchunk * pp * 32;   // partials
   b += 4 * P * 8 + 2 * P;               // H, S, stats, alive/complete
+  b += 16 * pp * 8 + 2 * P * 8;         // split-Gram partials, row scales
   b += pp * (8 + 1 + 8) + P * 4;        // T, T_state, H record, order
   b += (uint64_t)op.record_M_iters * pp * 8;
   if (!op.x_on_device) b += P * (uint64_t)n * (op.x_dtype == 1 ? 4 : 8);
@@ -289,6 +318,7 @@ lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam
 
   Allocs al;
   OwnedStream os;
+  PairTimer timer;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   try {
     if (o.device >= 0) HIPCHK(hipSetDevice(o.device));
@@ -299,13 +329,15 @@ lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam
       os.owned = true;
     }
     Fit f;
+    f.timer = &timer;
+    timer.on = o.profile != 0;
     f.o = o;
     f.s = os.s;
     f.p = (int)p;
     f.n = n;
     f.mixed = o.precision == LINGAM_PREC_MIXED;
     f.threshold = o.use_threshold != 0;
-    f.gamma0 = o.gamma0 > 0 ? o.gamma0 : 1e-6;
+    f.gamma0 = o.gamma0 > 0 ? o.gamma0 : 0.0;  // 0 = adaptive
     f.gmult = o.gamma_mult > 1.0 ? o.gamma_mult : 4.0;
     f.pl = make_plan(n, o);
     Dev& d = f.d;
@@ -325,6 +357,7 @@ lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam
     d.M = al.get<double>(pp);
     d.S = al.get<double>(P);
     d.alive = al.get<uint8_t>(P);
+    d.alive_list = al.get<int32_t>(P);
     d.complete = al.get<uint8_t>(P);
     d.pend = al.get<uint8_t>(pp);
     d.nchunk_max = f.pl.nchunk;
@@ -337,6 +370,8 @@ lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam
     d.rec = o.record_M_iters;
     d.Mrec = d.rec > 0 ? al.get<double>((size_t)d.rec * pp) : nullptr;
     d.stats = al.get<double>(2 * P);
+    d.gram_slices_max = GRAM_SLICES_MAX;
+    d.Gp = al.get<double>((size_t)GRAM_SLICES_MAX * pp);
     d.forced_len = o.forced_len;
     int32_t* forced_dev = al.get<int32_t>(std::max<size_t>(1, (size_t)o.forced_len));
     d.forced = forced_dev;
@@ -401,8 +436,8 @@ lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam
         const int rf = (int)p - tf, buf = tf & 1;
         HIPCHK(launch_resume(d, f.s));
         for (int extra = 0;; ++extra) {
-          HIPCHK(launch_pair_band(d, buf, full_band(rf, f.pl), f.mixed, f.s));
-          HIPCHK(launch_score(d, buf, rf, f.pl.nchunk, 1, tf, f.gmult, f.s));
+          f.pair(buf, full_band(rf, f.pl));
+          HIPCHK(launch_score(d, buf, full_band(rf, f.pl), 1, tf, f.gmult, f.s));
           c = f.read_ctl();
           if (c.status != ST_OK || c.done) break;
           if (extra > rf + 8) throw HipFail{hipErrorUnknown, "threshold rounds did not terminate", __LINE__};
@@ -431,6 +466,10 @@ lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam
     out->pair_samples = c.pairs_evaluated * (uint64_t)n;
     out->pairs_computed = c.pairs_computed;
     out->threshold_rounds = c.rounds_total;
+    if (timer.on) {
+      out->seconds_pair_kernel = timer.total_seconds();
+      out->pair_kernel_launches = timer.launches;
+    }
     out->bands = c.bands_total;
     int it = 0;
     for (int64_t k = 0; k < p; ++k) if (order[(size_t)k] >= 0) ++it;

@@ -25,6 +25,7 @@
 #include "lingam_internal.h"
 
 #include <algorithm>
+
 #include <cmath>
 #include <type_traits>
 
@@ -183,13 +184,18 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int GT = 32;   // output tile (GT x GT) per work-group, 4 waves of 16 x 16
 constexpr int GK = 64;   // samples per LDS stage
 
-__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ Z, int64_t ldz, int64_t n,
-                                              int r, double* __restrict__ Sig, int ldsig,
-                                              double* __restrict__ dsc, const Ctl* ctl) {
+// Partial Gram of one sample slice: Gp[slice][i][j] = sum_{k in slice} z_i[k] z_j[k]
+// for the upper-triangular 32 x 32 tile given by blockIdx.x (i <= j).  Each
+// LDS stage is summed by the matrix cores into a fresh accumulator and then
+// added into a Kahan-compensated total; the next stage is fetched into
+// registers while the current one is multiplied.
+__global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__ Z, int64_t ldz,
+                                                      int64_t n, int r, int64_t slice_len,
+                                                      double* __restrict__ Gp, int ldg,
+                                                      const Ctl* ctl) {
   if (halted(ctl)) return;
   __shared__ double As[GT][GK + 1];
   __shared__ double Bs[GT][GK + 1];
-  // upper-triangular tile (ti <= tj) from the linear block index
   const int nt = (r + GT - 1) / GT;
   int ti = 0, rem = blockIdx.x;
   while (rem >= nt - ti) { rem -= nt - ti; ++ti; }
@@ -197,22 +203,35 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ Z, int6
   const int i0 = ti * GT, j0 = tj * GT;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int wy = wave >> 1, wx = wave & 1;
-  // each LDS stage is summed by the matrix cores into a fresh accumulator and
-  // then added into a Kahan-compensated total, so the rounding error of the
-  // n-term dot products stays at the level of one stage
-  dbl4 tot = {0.0, 0.0, 0.0, 0.0}, comp = {0.0, 0.0, 0.0, 0.0};
-  const int64_t kmax = (n + GK - 1) / GK * GK;  // <= ldz (zero padded)
-  for (int64_t k0 = 0; k0 < kmax; k0 += GK) {
-    // 32 rows x 64 samples per matrix: 8 doubles per thread
+  const int64_t kbeg = (int64_t)blockIdx.y * slice_len;
+  const int64_t kend = min((int64_t)((n + GK - 1) / GK * GK), kbeg + slice_len);  // <= ldz
+  // this thread's 8 + 8 elements of a stage
+  constexpr int PER = (GT * GK) / 256;
+  const int row0 = threadIdx.x / (GK / PER), col0 = (threadIdx.x % (GK / PER)) * PER;
+  const bool ra = i0 + row0 < r, rb = j0 + row0 < r;
+  const double* za = Z + (int64_t)(i0 + row0) * ldz + col0;
+  const double* zb = Z + (int64_t)(j0 + row0) * ldz + col0;
+  double pa[PER], pb[PER];
+  auto fetch = [&](int64_t k0) {
 #pragma unroll
-    for (int e = 0; e < (GT * GK) / 256; ++e) {
-      const int idx = threadIdx.x + 256 * e;
-      const int row = idx / GK, col = idx % GK;
-      const int ra = i0 + row, rb = j0 + row;
-      As[row][col] = ra < r ? Z[(int64_t)ra * ldz + k0 + col] : 0.0;
-      Bs[row][col] = rb < r ? Z[(int64_t)rb * ldz + k0 + col] : 0.0;
+    for (int e = 0; e < PER; e += 2) {
+      double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+      if (ra) va = *reinterpret_cast<const double2*>(za + k0 + e);
+      if (rb) vb = *reinterpret_cast<const double2*>(zb + k0 + e);
+      pa[e] = va.x; pa[e + 1] = va.y;
+      pb[e] = vb.x; pb[e + 1] = vb.y;
+    }
+  };
+  dbl4 tot = {0.0, 0.0, 0.0, 0.0}, comp = {0.0, 0.0, 0.0, 0.0};
+  if (kbeg < kend) fetch(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += GK) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      As[row0][col0 + e] = pa[e];
+      Bs[row0][col0 + e] = pb[e];
     }
     __syncthreads();
+    if (k0 + GK < kend) fetch(k0 + GK);
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
@@ -230,24 +249,52 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ Z, int6
     __syncthreads();
   }
   // result layout of v_mfma_f64_16x16x4f64: lane holds rows lane/16 + 4v, column lane%16
-  const double inv = 1.0 / (double)(n - 1);
+  double* G = Gp + (int64_t)blockIdx.y * ldg * ldg;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int gi = i0 + wy * 16 + (lane >> 4) + 4 * v;
     const int gj = j0 + wx * 16 + (lane & 15);
-    if (gi < r && gj < r && gi <= gj) {
-      const double val = tot[v] * inv;
-      Sig[(int64_t)gi * ldsig + gj] = val;
-      Sig[(int64_t)gj * ldsig + gi] = val;
-      if (gi == gj) dsc[gi] = 1.0 / sqrt(val);
-    }
+    if (gi < r && gj < r && gi <= gj) G[(int64_t)gi * ldg + gj] = tot[v];
   }
+}
+
+// Sum the slices in a fixed order, scale by 1/(n-1), mirror, and set the row
+// scales d_i = 1/sqrt(G_ii).
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ Gp, int ldg, int nslice,
+                                                     int r, double n, double* __restrict__ Sig,
+                                                     double* __restrict__ dsc, const Ctl* ctl) {
+  if (halted(ctl)) return;
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j < i || j >= r) return;
+  double sum = 0.0;
+  for (int q = 0; q < nslice; ++q) sum += Gp[((int64_t)q * ldg + i) * ldg + j];
+  const double val = sum / (n - 1.0);
+  Sig[(int64_t)i * ldg + j] = val;
+  Sig[(int64_t)j * ldg + i] = val;
+  if (i == j) dsc[i] = 1.0 / sqrt(val);
+}
+
+int gram_slices(int r, int64_t n, int max_slices) {
+  const int nt = (r + GT - 1) / GT;
+  const int tiles = nt * (nt + 1) / 2;
+  int sl = (2048 + tiles - 1) / tiles;
+  const int64_t stages = (n + GK - 1) / GK;
+  sl = (int)std::min<int64_t>(sl, std::max<int64_t>(1, stages / 4));
+  return std::max(1, std::min(sl, max_slices));
 }
 
 hipError_t launch_gram(const Dev& d, int buf, int r, hipStream_t s) {
   const int nt = (r + GT - 1) / GT;
-  hipLaunchKernelGGL(k_gram, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, d.Z[buf], d.ldz, d.n, r,
-                     d.Sig[buf], d.p, d.dsc[buf], d.ctl);
+  const int sl = gram_slices(r, d.n, d.gram_slices_max);
+  const int64_t stages = (d.n + GK - 1) / GK;
+  const int64_t slice_len = (stages + sl - 1) / sl * GK;
+  hipLaunchKernelGGL(k_gram_partial, dim3(nt * (nt + 1) / 2, sl), dim3(256), 0, s, d.Z[buf], d.ldz, d.n, r,
+                     slice_len, d.Gp, d.p, d.ctl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((r + 255) / 256, r), dim3(256), 0, s, d.Gp, d.p, sl, r,
+                     (double)d.n, d.Sig[buf], d.dsc[buf], d.ctl);
   return hipGetLastError();
 }
 
@@ -291,8 +338,11 @@ hipError_t launch_entropy(const Dev& d, int buf, int r, int mixed, hipStream_t s
 // ============================================================================
 // iteration set-up: M = "not evaluated", S = 0, everyone below the threshold
 // ============================================================================
+// gamma0 > 0: that initial threshold in every iteration; gamma0 <= 0: adaptive,
+// `adapt` times the previous iteration's root score (the first iteration and a
+// zero previous score use 1e-6).
 __global__ void k_iter_init(double* M, uint8_t* pend, double* S, uint8_t* alive, uint8_t* complete,
-                            int r, int p, double gamma0, Ctl* ctl) {
+                            int32_t* alive_list, int r, int p, double gamma0, double adapt, Ctl* ctl) {
   if (halted(ctl)) return;
   const int64_t total = (int64_t)r * r;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -305,57 +355,43 @@ __global__ void k_iter_init(double* M, uint8_t* pend, double* S, uint8_t* alive,
     S[x] = 0.0;
     alive[x] = 1;
     complete[x] = 0;
+    alive_list[x] = x;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->gamma = gamma0;
+    double g = gamma0;
+    if (!(g > 0.0)) {
+      const double prev = ctl->last_root_S;
+      g = prev > 0.0 ? adapt * prev : 1e-6;
+    }
+    ctl->gamma = g;
     ctl->done = 0;
     ctl->root = -1;
     ctl->round = 0;
-    ctl->score_arrive = 0;
+    ctl->n_alive = r;
   }
 }
 
-hipError_t launch_iter_init(const Dev& d, int r, double gamma0, hipStream_t s) {
+hipError_t launch_iter_init(const Dev& d, int r, double gamma0, double adapt, hipStream_t s) {
   const int64_t total = (int64_t)r * r;
   int blocks = (int)((total + 255) / 256);
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_iter_init, dim3(blocks), dim3(256), 0, s, d.M, d.pend, d.S, d.alive,
-                     d.complete, r, d.p, gamma0, d.ctl);
+                     d.complete, d.alive_list, r, d.p, gamma0, adapt, d.ctl);
   return hipGetLastError();
 }
 
 // ============================================================================
 // a4/a5: the pair kernel
 // ============================================================================
-// Oriented tile `t` of a band -> (A, B) block indices.
-__device__ __forceinline__ void band_tile(const BandArgs& a, int t, int& A, int& B) {
-  int d = a.d0;
-  for (;;) {
-    const int c = tiles_at_distance(a.nb, d, a.both);
-    if (t < c) break;
-    t -= c;
-    ++d;
-  }
-  if (d == 0) {
-    A = B = t;
-  } else if (2 * d < a.nb) {
-    const int base = t % a.nb, orient = t / a.nb;
-    const int other = (base + d) % a.nb;
-    if (a.both) {
-      A = orient ? other : base;
-      B = orient ? base : other;
-    } else {
-      A = min(base, other);
-      B = max(base, other);
-    }
-  } else {  // 2d == nb
-    const int half = a.nb / 2;
-    const int base = t % half, orient = t / half;
-    A = orient ? base + d : base;
-    B = orient ? base : base + d;
-  }
-}
+// Work of one band: every variable below the threshold ("alive", compacted
+// in alive_list) is compared with every variable of the band's target blocks
+// [tb0, tb0 + ntb) -- a block form of one step of the paper's workers, each
+// comparing itself with its next targets.  A pair is evaluated once: when
+// both variables are alive rows of the band (the row's block is a target
+// block too) only the lower position evaluates it.  A work-group holds RG
+// alive rows (one per wave) against one target block B and one sample chunk;
+// the 8 rows of B are staged through LDS and shared by all of its waves.
 
 // Reduce 32 per-lane values to 32 totals spread over the wave: afterwards
 // lane l holds total number (l >> 1) & 31 (both lanes of a pair hold it).
@@ -398,47 +434,73 @@ __device__ __forceinline__ double reduce_scatter32(double (&v)[32]) {
   return v[0] + __shfl_xor(v[0], 1, 64);
 }
 
-template <bool MIXED>
-__global__ __launch_bounds__(PAIR_THREADS) void k_pair_band(
+template <bool MIXED, int RG>
+__global__ __launch_bounds__(64 * RG) void k_pair_band(
     const double* __restrict__ Z, int64_t ldz, int64_t n, const double* __restrict__ Sig,
-    const double* __restrict__ dsc, const double* __restrict__ M, const uint8_t* __restrict__ alive, double* __restrict__ P,
-    uint8_t* __restrict__ pend, const int32_t* __restrict__ idx, int p, BandArgs a, Ctl* ctl) {
-  __shared__ double lds[2 * TB][SUB];
-  __shared__ uint32_t s_mask[PAIR_WAVES];
-  __shared__ int s_stop;
-  // the stop decision is read once and shared, so the whole work-group
-  // leaves together even if another work-group raises an error meanwhile
-  if (threadIdx.x == 0) s_stop = halted(ctl) || ctl->done;
+    const double* __restrict__ dsc, const double* __restrict__ M,
+    const uint8_t* __restrict__ alive, const int32_t* __restrict__ alive_list,
+    double* __restrict__ P, uint8_t* __restrict__ pend, const int32_t* __restrict__ idx, int p,
+    BandArgs a, Ctl* ctl) {
+  __shared__ double lds[TB][PSUB];   // the 8 rows of target block B, one stage
+  __shared__ uint32_t s_mask[RG];
+  __shared__ int s_stop, s_m;
+  // XCD-aware order: consecutive logical work-groups (same chunk and target
+  // block, different row groups) land on the same XCD and share its L2
+  const int per = gridDim.x / 8;
+  const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int G = a.ntb * a.nchunk * a.nrg;
+  if (logical >= G) return;
+  const int g = logical % a.nrg;
+  const int tb = (logical / a.nrg) % a.ntb;
+  const int chunk = logical / (a.nrg * a.ntb);
+  const int B = a.tb0 + tb;
+  // the stop decision and the alive count are read once and shared, so the
+  // whole work-group decides together
+  if (threadIdx.x == 0) {
+    s_stop = halted(ctl) || ctl->done;
+    s_m = ctl->n_alive;
+  }
+  __syncthreads();
+  const int m = s_m;
+  if (s_stop || g * RG >= m) return;
 
-  const int tile = blockIdx.x % a.ntiles;
-  const int chunk = blockIdx.x / a.ntiles;
-  int A, B;
-  band_tile(a, tile, A, B);
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int lane = threadIdx.x % 64;
   const int r = a.r;
-  const int v = A * TB + wave;
+  const int q = g * RG + wave;
+  const int v = q < m ? alive_list[q] : -1;
 
-  // which of the 8 pairs (v, w in B) this wave must evaluate (wave-uniform)
+  // which of the 8 pairs (v, w in B) this wave evaluates (wave-uniform)
   uint32_t mask = 0;
-  if (v < r && alive[v]) {
+  if (v >= 0) {
+    const int bv = v / TB;
+    const bool v_in_targets = bv >= a.tb0 && bv < a.tb0 + a.ntb;
 #pragma unroll
     for (int j = 0; j < TB; ++j) {
       const int w = B * TB + j;
       if (w >= r || w == v) continue;
       if (!__builtin_isnan(M[(int64_t)v * p + w])) continue;
-      const bool w_alive = alive[w] != 0;
-      const bool take = !w_alive || (A < B) || (A == B && v < w);
-      if (take) mask |= 1u << j;
+      const bool w_row = alive[w] != 0 && v_in_targets;  // w also a row of this band
+      if (!w_row || v < w) mask |= 1u << j;
     }
   }
+  mask = __builtin_amdgcn_readfirstlane(mask);
   if (lane == 0) s_mask[wave] = mask;
   __syncthreads();
-  uint32_t any = 0;
+  // waves without work end here; a barrier waits only for the waves still
+  // running, so they do not hold the work-group's slots for nothing
+  if (mask == 0) return;
+  int n_act = 0, rank = 0;
 #pragma unroll
-  for (int w = 0; w < PAIR_WAVES; ++w) any |= s_mask[w];
-  if (any == 0 || s_stop) return;  // uniform over the work-group
+  for (int w = 0; w < RG; ++w) {
+    if (s_mask[w]) {
+      n_act += 1;
+      if (w < wave) rank += 1;
+    }
+  }
 
-  // per-pair regression coefficient b = Sigma_vw and scale s = 1/sqrt(1 - b^2)
+  // per-pair regression coefficient b (correlation of the normalised rows)
+  // and scale s = 1/sqrt(1 - b^2) (Eq. var_update)
   double bj[TB], sj[TB];
 #pragma unroll
   for (int j = 0; j < TB; ++j) {
@@ -459,6 +521,8 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_band(
 
   const int64_t k0 = (int64_t)chunk * a.chunk;
   const int64_t kend = min(n, k0 + (int64_t)a.chunk);
+  const double dv = dsc[v];
+  const double* zrow = Z + (int64_t)v * ldz;
 
   // accumulators: [j][0] lc(r_v), [j][1] g(r_v), [j][2] lc(r_w), [j][3] g(r_w)
   using acc_t = typename std::conditional<MIXED, float, double>::type;
@@ -474,50 +538,46 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_band(
     cg[j] = (float)(-0.5 * 1.4426950408889634074 * sj[j] * sj[j]);
   }
 
-  for (int64_t ks = k0; ks < kend; ks += SUB) {
-    const int cnt = (int)min((int64_t)SUB, kend - ks);
-    // stage rows of blocks A and B (16 x SUB doubles; ldz is a multiple of SUB)
-#pragma unroll
-    for (int e = 0; e < (2 * TB * SUB / 2) / PAIR_THREADS; ++e) {
-      const int idx = threadIdx.x + PAIR_THREADS * e;
-      const int row = idx / (SUB / 2), c2 = idx % (SUB / 2);
-      const int var = row < TB ? A * TB + row : B * TB + (row - TB);
+  for (int64_t ks = k0; ks < kend; ks += PSUB) {
+    const int cnt = (int)min((int64_t)PSUB, kend - ks);
+    // the active waves stage the 8 rows of block B (ldz is a multiple of PSUB)
+    for (int e = rank * 64 + lane; e < TB * PSUB / 2; e += n_act * 64) {
+      const int row = e / (PSUB / 2), c2 = e % (PSUB / 2);
+      const int var = B * TB + row;
       double2 val = make_double2(0.0, 0.0);
       if (var < r) {
         val = *reinterpret_cast<const double2*>(Z + (int64_t)var * ldz + ks + 2 * c2);
-        const double dv = dsc[var];
-        val.x *= dv;
-        val.y *= dv;
+        const double d = dsc[var];
+        val.x *= d;
+        val.y *= d;
       }
       *reinterpret_cast<double2*>(&lds[row][2 * c2]) = val;
     }
     __syncthreads();
-    if (mask) {
-      for (int i = 0; i < SUB / 64; ++i) {
-        const int k = i * 64 + lane;
-        if (k < cnt) {
-          const double zv = lds[wave][k];
 #pragma unroll
-          for (int j = 0; j < TB; ++j) {
-            const double zw = lds[TB + j][k];
-            const double rv = __builtin_fma(-bj[j], zw, zv);  // r_v^(w) / s
-            const double rw = __builtin_fma(-bj[j], zv, zw);  // r_w^(v) / s
-            if constexpr (MIXED) {
-              terms_mixed((float)rv, ca[j], cg[j], acc[j][0], acc[j][1]);
-              terms_mixed((float)rw, ca[j], cg[j], acc[j][2], acc[j][3]);
-            } else {
-              double t0 = acc[j][0], t1 = acc[j][1], t2 = acc[j][2], t3 = acc[j][3];
-              terms_f64(sj[j] * rv, t0, t1);
-              terms_f64(sj[j] * rw, t2, t3);
-              acc[j][0] = t0; acc[j][1] = t1; acc[j][2] = t2; acc[j][3] = t3;
-            }
+    for (int i = 0; i < PSUB / 64; ++i) {
+      const int k = i * 64 + lane;
+      if (k < cnt) {
+        const double zv = dv * zrow[ks + k];
+#pragma unroll
+        for (int j = 0; j < TB; ++j) {
+          const double zw = lds[j][k];
+          const double rv = __builtin_fma(-bj[j], zw, zv);  // r_v^(w) / s
+          const double rw = __builtin_fma(-bj[j], zv, zw);  // r_w^(v) / s
+          if constexpr (MIXED) {
+            terms_mixed((float)rv, ca[j], cg[j], acc[j][0], acc[j][1]);
+            terms_mixed((float)rw, ca[j], cg[j], acc[j][2], acc[j][3]);
+          } else {
+            double t0 = acc[j][0], t1 = acc[j][1], t2 = acc[j][2], t3 = acc[j][3];
+            terms_f64(sj[j] * rv, t0, t1);
+            terms_f64(sj[j] * rw, t2, t3);
+            acc[j][0] = t0; acc[j][1] = t1; acc[j][2] = t2; acc[j][3] = t3;
           }
         }
       }
     }
     __syncthreads();
   }
-  if (!mask) return;
 
   // convert to sum(log cosh u + ln 2) and sum(u exp(-u^2/2)), reduce over the wave
   double vals[32];
@@ -535,7 +595,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_band(
   }
   const double tot = reduce_scatter32(vals);
   if ((lane & 1) == 0) {
-    const int q = lane >> 1, j = q >> 2, c = q & 3;
+    const int qq = lane >> 1, j = qq >> 2, c = qq & 3;
     if (mask >> j & 1u) {
       const int w = B * TB + j;
       P[(((int64_t)chunk * p + v) * p + w) * 4 + c] = tot;
@@ -553,40 +613,70 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_band(
   }
 }
 
-hipError_t launch_pair_band(const Dev& d, int buf, const BandArgs& a, int mixed, hipStream_t s) {
-  dim3 g((unsigned)a.ntiles * (unsigned)a.nchunk), b(PAIR_THREADS);
-  if (mixed)
-    hipLaunchKernelGGL(k_pair_band<true>, g, b, 0, s, d.Z[buf], d.ldz, d.n, d.Sig[buf], d.dsc[buf], d.M, d.alive,
-                       d.P, d.pend, d.idx[buf], d.p, a, d.ctl);
+// Alive rows per work-group.  Large groups share each staged target block
+// among many rows (dense bands, where every variable is still alive); small
+// groups spread the few alive rows of later bands over more CUs.  The
+// grouping does not change any arithmetic.
+constexpr int RG_DENSE = 16;  // binary32 terms, <= 128 VGPRs for 16 waves per CU
+constexpr int RG_SPARSE = 4;
+
+template <bool MIXED, int RG>
+static void launch_pair_rg(const Dev& d, int buf, BandArgs a, hipStream_t s) {
+  a.nrg = (a.r + RG - 1) / RG;
+  const int G = a.ntb * a.nchunk * a.nrg;
+  const int grid = (G + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_pair_band<MIXED, RG>), dim3(grid), dim3(64 * RG), 0, s, d.Z[buf], d.ldz, d.n,
+                     d.Sig[buf], d.dsc[buf], d.M, d.alive, d.alive_list, d.P, d.pend, d.idx[buf], d.p, a,
+                     d.ctl);
+}
+
+hipError_t launch_pair_band(const Dev& d, int buf, const BandArgs& a, int mixed, int dense, hipStream_t s) {
+  if (mixed && dense)
+    launch_pair_rg<true, RG_DENSE>(d, buf, a, s);
+  else if (mixed)
+    launch_pair_rg<true, RG_SPARSE>(d, buf, a, s);
   else
-    hipLaunchKernelGGL(k_pair_band<false>, g, b, 0, s, d.Z[buf], d.ldz, d.n, d.Sig[buf], d.dsc[buf], d.M, d.alive,
-                       d.P, d.pend, d.idx[buf], d.p, a, d.ctl);
+    launch_pair_rg<false, RG_SPARSE>(d, buf, a, s);  // binary64 terms need more registers per lane
   return hipGetLastError();
 }
 
 // ============================================================================
 // a5/a6: tests, scores, threshold state, termination and root
 // ============================================================================
+// Rows whose tests can have changed in a band: the variables of the target
+// blocks, then the alive variables outside them.  One wave per row forms
+// the pending tests from the chunk partial sums and recomputes the row's
+// score in a fixed order.
 __global__ __launch_bounds__(256) void k_score(double* __restrict__ M, uint8_t* __restrict__ pend,
                                                const double* __restrict__ P, const double* __restrict__ H,
-                                               double* __restrict__ S, uint8_t* __restrict__ alive,
-                                               uint8_t* __restrict__ complete, int r, int p, int nchunk,
-                                               double n, int round_end, int t, double gamma_mult,
-                                               const int32_t* __restrict__ forced, int forced_len,
-                                               const int32_t* __restrict__ idx, Ctl* ctl) {
-  if (halted(ctl) || ctl->done) return;
-  __shared__ int s_last;
-  __shared__ double sh_d[256];
-  __shared__ int sh_i[256];
+                                               double* __restrict__ S, uint8_t* __restrict__ complete,
+                                               const int32_t* __restrict__ alive_list, int r, int p,
+                                               int nchunk, double n, int tb0, int ntb, const Ctl* ctl) {
+  __shared__ int s_stop, s_m;
+  if (threadIdx.x == 0) {
+    s_stop = halted(ctl) || ctl->done;
+    s_m = ctl->n_alive;
+  }
+  __syncthreads();
+  if (s_stop) return;
+  const int m = s_m;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int x = blockIdx.x * 4 + wave;
-  if (x < r) {
+  const int qrow = blockIdx.x * 4 + wave;
+  const int t_lo = tb0 * TB, t_hi = min(r, (tb0 + ntb) * TB);
+  int x = -1;
+  if (qrow < t_hi - t_lo) {
+    x = t_lo + qrow;
+  } else if (qrow - (t_hi - t_lo) < m) {
+    const int y = alive_list[qrow - (t_hi - t_lo)];
+    if (y < t_lo || y >= t_hi) x = y;
+  }
+  if (x >= 0) {
     double s = 0.0;
     int incomplete = 0;
     const double hx = H[x];
     for (int w = lane; w < r; w += 64) {
       if (w == x) continue;
-      double m;
+      double mv;
       if (pend[(int64_t)x * p + w]) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         for (int c = 0; c < nchunk; ++c) {
@@ -595,16 +685,16 @@ __global__ __launch_bounds__(256) void k_score(double* __restrict__ M, uint8_t* 
         }
         const double h_rx = happ_from_sums(a0, a1, n);  // H(r_x^(w))
         const double h_rw = happ_from_sums(a2, a3, n);  // H(r_w^(x))
-        m = (H[w] + h_rx) - (hx + h_rw);                // Eq. (Itest)
-        M[(int64_t)x * p + w] = m;
+        mv = (H[w] + h_rx) - (hx + h_rw);               // Eq. (Itest)
+        M[(int64_t)x * p + w] = mv;
         pend[(int64_t)x * p + w] = 0;
       } else {
-        m = M[(int64_t)x * p + w];
+        mv = M[(int64_t)x * p + w];
       }
-      if (__builtin_isnan(m)) {
+      if (__builtin_isnan(mv)) {
         incomplete = 1;
       } else {
-        const double neg = m < 0.0 ? m : 0.0;
+        const double neg = mv < 0.0 ? mv : 0.0;
         s += neg * neg;
       }
     }
@@ -615,95 +705,102 @@ __global__ __launch_bounds__(256) void k_score(double* __restrict__ M, uint8_t* 
       complete[x] = incomplete ? 0 : 1;
     }
   }
-  // last work-group to arrive takes the iteration-level decision
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(&ctl->score_arrive, 1u);
-    s_last = prev == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+}
 
+// Iteration-level decision after a band, on one wave (ballots and shuffles):
+// the termination test, the threshold update of a round that ended without
+// a root, the root, the next band's threshold state and the compacted alive
+// list.  Its own launch orders it after every row of the score kernel.
+__global__ __launch_bounds__(64) void k_decide(const double* __restrict__ S, uint8_t* __restrict__ alive,
+                                               const uint8_t* __restrict__ complete,
+                                               int32_t* __restrict__ alive_list, int r, int round_end, int t,
+                                               double gamma_mult, const int32_t* __restrict__ forced,
+                                               int forced_len, const int32_t* __restrict__ idx, Ctl* ctl) {
+  if (halted(ctl) || ctl->done) return;
+  const int lane = threadIdx.x;
   double gamma = ctl->gamma;
-  int done = 0, root = -1;
+  int done = 0;
   for (int guard = 0; guard < 4096; ++guard) {
     // termination: some complete score <= gamma, every incomplete score > gamma
-    int cand = 0, blocked = 0, all_above = 1;
-    for (int y = threadIdx.x; y < r; y += 256) {
-      const double sy = S[y];
-      const int cy = complete[y];
-      if (sy <= gamma) {
-        all_above = 0;
-        if (cy) cand = 1; else blocked = 1;
+    int cand = 0, blocked = 0, below = 0;
+    for (int y = lane; y < r; y += 64) {
+      if (S[y] <= gamma) {
+        below = 1;
+        if (complete[y]) cand = 1; else blocked = 1;
       }
     }
-    cand = __syncthreads_or(cand);
-    blocked = __syncthreads_or(blocked);
-    all_above = __syncthreads_and(all_above);
+    cand = __any(cand);
+    blocked = __any(blocked);
+    below = __any(below);
     if (cand && !blocked) { done = 1; break; }
-    if (round_end && all_above) { gamma *= gamma_mult; continue; }
+    if (round_end && !below) { gamma = gamma > 0.0 ? gamma * gamma_mult : 1e-300; continue; }
     break;
   }
+  int root = -1;
   if (done) {
     // root = argmin S over complete variables, lowest position on ties
     double best = INFINITY;
     int bi = 0x7fffffff;
-    for (int y = threadIdx.x; y < r; y += 256) {
+    for (int y = lane; y < r; y += 64) {
       if (!complete[y]) continue;
       const double sy = S[y];
       if (sy < best || (sy == best && y < bi)) { best = sy; bi = y; }
     }
-    sh_d[threadIdx.x] = best;
-    sh_i[threadIdx.x] = bi;
-    __syncthreads();
-    for (int h = 128; h >= 1; h >>= 1) {
-      if (threadIdx.x < h) {
-        const double o = sh_d[threadIdx.x + h];
-        const int oi = sh_i[threadIdx.x + h];
-        if (o < sh_d[threadIdx.x] || (o == sh_d[threadIdx.x] && oi < sh_i[threadIdx.x])) {
-          sh_d[threadIdx.x] = o;
-          sh_i[threadIdx.x] = oi;
-        }
-      }
-      __syncthreads();
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob < best || (ob == best && oi < bi)) { best = ob; bi = oi; }
     }
-    root = sh_i[0];
+    root = bi;
     if (t < forced_len) {
       // teacher forcing: the root is given; find its position
-      __shared__ int s_pos;
-      if (threadIdx.x == 0) s_pos = -1;
-      __syncthreads();
-      for (int y = threadIdx.x; y < r; y += 256)
-        if (idx[y] == forced[t]) s_pos = y;
-      __syncthreads();
-      root = s_pos;
+      int pos = -1;
+      for (int y = lane; y < r; y += 64)
+        if (idx[y] == forced[t]) pos = y;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) pos = max(pos, __shfl_xor(pos, off, 64));
+      root = pos;
     }
   }
-  for (int y = threadIdx.x; y < r; y += 256) alive[y] = S[y] <= gamma ? 1 : 0;
-  if (threadIdx.x == 0) {
+  // threshold state for the next band, and the compacted alive list
+  int base = 0;
+  for (int y0 = 0; y0 < r; y0 += 64) {
+    const int y = y0 + lane;
+    const int a = y < r && S[y] <= gamma ? 1 : 0;
+    if (y < r) alive[y] = (uint8_t)a;
+    const unsigned long long bal = __ballot(a);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (a) alive_list[base + before] = y;
+    base += __popcll(bal);
+  }
+  if (lane == 0) {
     ctl->gamma = gamma;
+    ctl->n_alive = base;
     if (done) {
       if (root < 0) {
         raise_error(ctl, ST_INVALID, -1, -1);
       } else {
         ctl->root = root;
+        ctl->last_root_S = S[root];
         ctl->done = 1;
       }
     } else if (round_end) {
       ctl->round += 1;
     }
     ctl->bands_total += 1;
-    ctl->score_arrive = 0;
   }
 }
 
-hipError_t launch_score(const Dev& d, int buf, int r, int nchunk, int round_end, int t,
+hipError_t launch_score(const Dev& d, int buf, const BandArgs& a, int round_end, int t,
                         double gamma_mult, hipStream_t s) {
-  hipLaunchKernelGGL(k_score, dim3((r + 3) / 4), dim3(256), 0, s, d.M, d.pend, d.P, d.H, d.S,
-                     d.alive, d.complete, r, d.p, nchunk, (double)d.n, round_end, t, gamma_mult,
-                     d.forced, d.forced_len, d.idx[buf], d.ctl);
+  const int rows = std::min(a.r, a.ntb * TB) + a.r;
+  hipLaunchKernelGGL(k_score, dim3((rows + 3) / 4), dim3(256), 0, s, d.M, d.pend, d.P, d.H, d.S,
+                     d.complete, d.alive_list, a.r, d.p, a.nchunk, (double)d.n, a.tb0, a.ntb, d.ctl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, s, d.S, d.alive, d.complete, d.alive_list, a.r,
+                     round_end, t, gamma_mult, d.forced, d.forced_len, d.idx[buf], d.ctl);
   return hipGetLastError();
 }
 

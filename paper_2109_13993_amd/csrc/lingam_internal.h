@@ -12,8 +12,12 @@ namespace lingam {
 constexpr int TB = 8;
 constexpr int PAIR_WAVES = TB;
 constexpr int PAIR_THREADS = 64 * PAIR_WAVES;
-// Samples staged through LDS per step (16 rows x SUB doubles = 32 KiB).
+// Row stride unit of the stored data (doubles); every sample range a kernel
+// stages starts at a multiple of it.
 constexpr int SUB = 256;
+// Samples of the 8 target rows staged through LDS per step of the pair
+// kernel (8 x PSUB doubles = 8 KiB).
+constexpr int PSUB = 128;
 // Samples per work-group chunk: at most 32 per lane, so the binary32 lane
 // sums of the mixed mode never run over more than 32 terms.
 constexpr int CHUNK_DEFAULT = 2048;
@@ -34,8 +38,9 @@ struct Ctl {
   int32_t status;       // Status of the first error
   int32_t bad_i, bad_j; // compacted positions (pair error) or original index (row error)
   int32_t round;        // threshold round of the current iteration
-  uint32_t score_arrive;  // arrival counter of the score kernel (last work-group decides)
   uint32_t pad0;
+  int32_t n_alive;        // entries of the alive list (variables with S <= gamma)
+  double last_root_S;     // score of the previous iteration's root (adaptive gamma0)
   unsigned long long pairs_evaluated;
   unsigned long long pairs_computed;
   unsigned long long rounds_total;
@@ -59,6 +64,7 @@ struct Dev {
   double* M = nullptr;       // p x p test matrix of the iteration (NaN = not evaluated)
   double* S = nullptr;       // [p] scores (sum of min(0, M)^2 over evaluated pairs)
   uint8_t* alive = nullptr;  // [p] S <= gamma at the last snapshot
+  int32_t* alive_list = nullptr;  // [p] positions with alive = 1, ascending
   uint8_t* complete = nullptr;  // [p] every pair of the row evaluated
   uint8_t* pend = nullptr;   // p x p: partial sums written, M not yet formed
   double* P = nullptr;       // [nchunk_max][p][p][4] per-chunk partial sums
@@ -73,17 +79,19 @@ struct Dev {
   const int32_t* forced = nullptr;  // device copy of the forced prefix
   int forced_len = 0;
   double* stats = nullptr;   // [2*p] per-row mean/variance of the input (diagnostics)
+  double* Gp = nullptr;      // [gram_slices_max][p][p] per-slice partial Gram
+  int gram_slices_max = 1;
 };
 
-// Parameters of one band launch of the pair kernel.
+// Parameters of one band launch of the pair kernel: every alive variable is
+// compared with the variables of target blocks [tb0, tb0 + ntb).
 struct BandArgs {
   int r;          // remaining variables
-  int nb;         // tile blocks, ceil(r / TB)
-  int d0, d1;     // block-distance range of the band
-  int both;       // 1 = both orientations of every block pair, 0 = canonical one only
-  int ntiles;     // oriented tiles in the band
-  int nchunk;     // sample chunks per tile
+  int nb;         // blocks of TB variables, ceil(r / TB)
+  int tb0, ntb;   // target blocks of the band
+  int nchunk;     // sample chunks
   int chunk;      // samples per chunk
+  int nrg;        // row groups (set by the launcher)
 };
 
 // ---- launch wrappers (kernels.hip) --------------------------------------
@@ -91,9 +99,9 @@ hipError_t launch_standardize(const void* X, int x_dtype, int layout, int64_t n,
                               const Dev& d, hipStream_t s);
 hipError_t launch_gram(const Dev& d, int buf, int r, hipStream_t s);
 hipError_t launch_entropy(const Dev& d, int buf, int r, int mixed, hipStream_t s);
-hipError_t launch_iter_init(const Dev& d, int r, double gamma0, hipStream_t s);
-hipError_t launch_pair_band(const Dev& d, int buf, const BandArgs& a, int mixed, hipStream_t s);
-hipError_t launch_score(const Dev& d, int buf, int r, int nchunk, int round_end, int t,
+hipError_t launch_iter_init(const Dev& d, int r, double gamma0, double adapt, hipStream_t s);
+hipError_t launch_pair_band(const Dev& d, int buf, const BandArgs& a, int mixed, int dense, hipStream_t s);
+hipError_t launch_score(const Dev& d, int buf, const BandArgs& a, int round_end, int t,
                         double gamma_mult, hipStream_t s);
 hipError_t launch_finish_iter(const Dev& d, int buf, int r, int t, hipStream_t s);
 hipError_t launch_record_M(const Dev& d, int buf, int r, int t, hipStream_t s);
@@ -103,12 +111,5 @@ hipError_t launch_resume(const Dev& d, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t count, uint8_t v, hipStream_t s);
 
-// Number of oriented tiles of block distance d (nb blocks).
-__host__ __device__ inline int tiles_at_distance(int nb, int d, int both) {
-  if (d == 0) return nb;
-  if (2 * d < nb) return both ? 2 * nb : nb;
-  if (2 * d == nb) return both ? nb : nb / 2;
-  return 0;
-}
 
 }  // namespace lingam

@@ -85,7 +85,7 @@ def test_defaults_and_status_strings(lib):
     o = lg.default_opts()
     assert o.struct_size == ctypes.sizeof(lg.LingamOpts)
     assert o.use_threshold == 1 and o.precision == 0 and o.cov_refresh_every == 1
-    assert o.gamma0 == 1e-6 and o.gamma_mult == 4.0
+    assert o.gamma0 == 0.0 and o.gamma_mult == 4.0
     for s in range(7):
         assert len(lg.status_string(s)) > 0
     assert lg.workspace_size(20000, 500) > 2 * 500 * 20000 * 8

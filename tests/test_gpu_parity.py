@@ -98,17 +98,18 @@ def test_small_chunks_and_bands_fp64_parity():
     # many sample chunks per tile and one block distance per band
     ds = synth.lingam_dataset(40, 5000, 0.2, "laplace", rng=np.random.default_rng(7))
     g, o = full_parity(ds.X, M_iters=3, chunk_samples=512)
-    t = lg.fit_order(ds.X, precision="fp64", chunk_samples=512, band_tiles=1)
+    t = lg.fit_order(ds.X, precision="fp64", chunk_samples=512, band_blocks=1)
     assert list(t.order) == list(o["order"])
 
 
 def test_threshold_keeps_order_and_complete_scores():
-    # small bands (one block distance each) so the threshold actually prunes
+    # one target block per band so the threshold has many chances to prune
     for seed, (p, n) in enumerate([(10, 1000), (27, 3001), (60, 4000)]):
         ds = synth.lingam_dataset(p, n, 0.3, "mixed", rng=np.random.default_rng(50 + seed))
         off = lg.fit_order(ds.X, use_threshold=False)
-        for g0, c, bt in ((1e-6, 4.0, 1), (1e-9, 2.0, 1), (1e-3, 10.0, 1), (1e-6, 4.0, 0)):
-            on = lg.fit_order(ds.X, use_threshold=True, gamma0=g0, gamma_mult=c, band_tiles=bt)
+        for g0, c, bt in ((1e-6, 4.0, 1), (1e-9, 2.0, 1), (1e-3, 10.0, 1), (0.0, 4.0, 1),
+                          (0.0, 1.5, 2), (1e-6, 4.0, 0)):
+            on = lg.fit_order(ds.X, use_threshold=True, gamma0=g0, gamma_mult=c, band_blocks=bt)
             assert list(on.order) == list(off.order)
             comp = on.T_state == 1
             pruned = on.T_state == 2
@@ -116,9 +117,9 @@ def test_threshold_keeps_order_and_complete_scores():
             assert np.all(on.T[pruned] >= off.T[pruned])           # partial S <= full S
             assert np.array_equal(on.T_state > 0, off.T_state > 0)
             assert on.pairs_evaluated <= off.pairs_evaluated
-            _log("p=%d gamma0=%g c=%g band_tiles=%d: pairs %d / %d, rounds %d, bands %d" % (
+            _log("p=%d gamma0=%g c=%g band_blocks=%d: pairs %d / %d, rounds %d, bands %d" % (
                 p, g0, c, bt, on.pairs_evaluated, off.pairs_evaluated, on.threshold_rounds, on.bands))
-            if p >= 27 and bt == 1:
+            if p >= 27 and bt == 1 and g0 != 1e-3:
                 assert on.pairs_evaluated < off.pairs_evaluated
 
 
@@ -130,7 +131,7 @@ def test_config2_fp64_parity():
     check_fp64(g, o, 100)
     on = lg.fit_order(ds.X, precision="fp64")   # default: threshold on
     assert list(on.order) == list(o["order"])
-    small = lg.fit_order(ds.X, precision="fp64", band_tiles=8)
+    small = lg.fit_order(ds.X, precision="fp64", band_blocks=1)
     assert list(small.order) == list(o["order"])
     assert small.pairs_evaluated < g.pairs_evaluated
 
