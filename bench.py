@@ -30,8 +30,26 @@ PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
 SLOTS_PER_PAIR_SAMPLE_MIXED = 2 + 2 + 2 * 7 + 6 * 2
 
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_kernel_p500_n20000.traffic.json")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per pair-kernel launch from the committed rocprofv3 counter
+    summary, or None if the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        src = open(os.path.join(ROOT, "paper_2109_13993_amd", "csrc", "kernels.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("kernels_hip_sha256"):
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def timed_runs(lg, X, precision, steps, warmup, **kw):
@@ -68,6 +86,8 @@ def main():
     ap.add_argument("--cpu-vars", type=int, default=160, help="variables in the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -76,6 +96,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "copies": 5}))
+        return
 
     import paper_2109_13993_amd as lg
     from paper_2109_13993_amd import synth
@@ -114,7 +144,7 @@ def main():
                                "Laplace noise, seeded", "p": p, "n": n, "precision": "mixed",
                    "threshold": True},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
-                     "unit": "Tlane-slot/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": None,
+                     "unit": "Tlane-slot/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": measured_traffic(),
                      "kernel": "k_pair_band<mixed>", "slots_per_pair_sample": SLOTS_PER_PAIR_SAMPLE_MIXED,
                      "pair_kernel_ms_per_step": kern_s * 1e3, "launches_per_step": launches},
         "pairs_evaluated": res_mix[-1].pairs_evaluated,
