@@ -5,8 +5,8 @@
  * from observational data, the first (order-finding) step of DirectLiNGAM
  * that ParaLiNGAM accelerates (Shahbazinia, Salehkaleybar, Hashemi,
  * "ParaLiNGAM", arXiv 2109.13993):
- *   - Alg. 1 lines 1-7 / Alg. 3: p iterations of "find the root, append it to
- *     K, remove it from U, regress it out of the remaining variables";
+ *   - Alg. 1 / Alg. 3: p iterations of: find the root, append it to K,
+ *     remove it from U, regress it out of the remaining variables;
  *   - Alg. 2: the root is the variable of minimum score
  *     S_i = sum_j min(0, I(x_i, x_j, r_i^(j), r_j^(i)))^2, with the
  *     likelihood-ratio test of Eq. (Itest) and the entropy approximation of

@@ -101,7 +101,7 @@ def compare(xi, xj):
 
 
 def fit_order(X, max_roots=0, forced_order=None, nthreads=0, M_iters=0, want_T=True):
-    """Plain DirectLiNGAM causal-order search (Alg. 1 lines 1-7, Alg. 2).
+    """Plain DirectLiNGAM causal-order search (Alg. 1 without the estimate of B, Alg. 2).
 
     Returns dict(order=int32[p] (-1 past the last root), T=float64[p,p] or None
     (T[t, v] = -S_v at iteration t, NaN if v is not in U_t), H=float64[p,p] or None

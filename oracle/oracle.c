@@ -9,9 +9,9 @@
  * it, and it shares no code, header or constant table with the GPU library.
  *
  * What is computed (all arithmetic in IEEE binary64):
- *   - Alg. 1 (DirectLiNGAM), lines 1-7: repeat FindRoot, append the root to
- *     the causal order K, remove it from U and regress it out of the data.
- *     Line 8 (estimating B) is not part of this search.
+ *   - Alg. 1 (DirectLiNGAM): repeat FindRoot, append the root to the causal
+ *     order K, remove it from U and regress it out of the data.  Its final
+ *     step (estimating B from K) is not part of this search.
  *   - Alg. 2 (FindRoot): for every ordered pair (i, j) of remaining
  *     variables, normalise x_i and x_j, regress each on the other, normalise
  *     both residuals and add min(0, I)^2 to the score of i; the root is the
@@ -31,7 +31,7 @@
  *   - The test is grouped as (H(x_j) + H(r_i^(j))) - (H(x_i) + H(r_j^(i))),
  *     so the reverse test is the exact negation (messaging, Sec. 3.1).
  *   - The loop of Alg. 1 runs until U is empty; the last variable is
- *     appended without a comparison (Alg. 2, lines 1-3).
+ *     appended without a comparison (Alg. 2).
  *   - Ties in the minimum score go to the variable with the lowest original
  *     index (U keeps the original order).
  *   - A zero or non-finite row variance, or a residual variance <= 1e-12,
@@ -272,7 +272,7 @@ static int normalize_and_entropy(const double* X, double* Z, int64_t n, const in
   return status;
 }
 
-/* RegressRoot (Alg. 1, line 7): x_u <- x_u - cov(x_u, x_root)/var(x_root) x_root
+/* RegressRoot (Alg. 1): x_u <- x_u - cov(x_u, x_root)/var(x_root) x_root
  * for every u remaining in U (root already removed).  Works on the
  * normalised rows Z and writes the residuals back into X. */
 static void regress_root(double* X, const double* Z, int64_t n, const int32_t* U, int32_t r,
@@ -291,7 +291,7 @@ static void regress_root(double* X, const double* Z, int64_t n, const int32_t* U
 }
 
 /*
- * Full causal-order search (Alg. 1 lines 1-7 with Alg. 2).
+ * Full causal-order search (Alg. 1 without its final estimate of B, with Alg. 2).
  *   X         : p x n input, row i = the n samples of variable i (read only)
  *   max_roots : 0 = full order, else stop after this many scored roots
  *   forced    : optional prefix of roots to follow instead of argmax
@@ -344,7 +344,7 @@ int oracle_fit_order(const double* X, int64_t n, int64_t p, int32_t max_roots,
   }
   memcpy(W, X, sizeof(double) * pn);
   int32_t r = (int32_t)p;
-  for (int32_t a = 0; a < r; ++a) U[a] = a;  /* Alg. 1 line 1 */
+  for (int32_t a = 0; a < r; ++a) U[a] = a;  /* U = all variables (Alg. 1) */
 
   int status = OR_OK;
   int32_t t = 0;
@@ -352,7 +352,7 @@ int oracle_fit_order(const double* X, int64_t n, int64_t p, int32_t max_roots,
   while (r > 0 && t < limit) {
     int32_t root;
     if (r == 1) {
-      /* Alg. 2 lines 1-3: a single remaining variable is the root. */
+      /* a single remaining variable is the root (Alg. 2) */
       root = 0;
       if (forced && t < forced_len && forced[t] != U[0]) { status = OR_E_INVALID; break; }
       if (T) T[(int64_t)t * p + U[0]] = 0.0;
@@ -386,18 +386,18 @@ int oracle_fit_order(const double* X, int64_t n, int64_t p, int32_t max_roots,
         for (int32_t a = 0; a < r; ++a) if (U[a] == forced[t]) root = a;
         if (root < 0) { status = OR_E_INVALID; break; }
       } else {
-        /* Alg. 2 line 17: argmin S, first (lowest index) on ties. */
+        /* root = argmin S (Alg. 2), first (lowest index) on ties */
         root = 0;
         for (int32_t a = 1; a < r; ++a) if (S[a] < S[root]) root = a;
       }
     }
     int32_t root_var = U[root];
-    order[t] = root_var;              /* Alg. 1 line 5 */
+    order[t] = root_var;              /* append the root to K */
     used[root_var] = 1;
-    for (int32_t a = root; a + 1 < r; ++a) U[a] = U[a + 1];  /* line 6 */
+    for (int32_t a = root; a + 1 < r; ++a) U[a] = U[a + 1];  /* remove it from U */
     --r;
     ++t;
-    if (r > 0 && t < limit) regress_root(W, Z, n, U, r, root_var);  /* line 7 */
+    if (r > 0 && t < limit) regress_root(W, Z, n, U, r, root_var);  /* RegressRoot */
   }
   free(W); free(Z); free(U); free(H); free(S); free(Mr); free(Br); free(used);
   return status;

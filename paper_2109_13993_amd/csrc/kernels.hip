@@ -928,7 +928,7 @@ hipError_t launch_update(const Dev& d, int buf, int r, int refresh, hipStream_t 
   return hipSuccess;
 }
 
-// Last remaining variable: appended without a comparison (Alg. 2, lines 1-3).
+// Last remaining variable: appended without a comparison (Alg. 2).
 __global__ void k_last(const int32_t* idx, int p, int t, int32_t* order, double* Tall, uint8_t* Tstate,
                        const Ctl* ctl) {
   if (halted(ctl)) return;
