@@ -393,67 +393,52 @@ hipError_t launch_iter_init(const Dev& d, int r, double gamma0, double adapt, hi
 // alive rows (one per wave) against one target block B and one sample chunk;
 // the 8 rows of B are staged through LDS and shared by all of its waves.
 
-// Reduce 32 per-lane values to 32 totals spread over the wave: afterwards
-// lane l holds total number (l >> 1) & 31 (both lanes of a pair hold it).
-__device__ __forceinline__ double reduce_scatter32(double (&v)[32]) {
+// Reduce NV per-lane values (NV a power of two, <= 32) to NV totals spread
+// over the wave: afterwards lane l holds total number (l >> (6 - log2 NV)) &
+// (NV - 1).  Lanes are combined by lane-index bit 5 first and bit 0 last
+// whatever NV is, so (addition being commutative) every total is the same
+// binary64 value as a full butterfly sum of that value alone.
+template <int NV>
+__device__ __forceinline__ double reduce_scatter(double (&v)[NV]) {
   const int lane = threadIdx.x & 63;
+  int mask = 32;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const bool hi = lane & 32;
-    const double keep = hi ? v[16 + i] : v[i];
-    const double send = hi ? v[i] : v[16 + i];
-    v[i] = keep + __shfl_xor(send, 32, 64);
-  }
+  for (int cnt = NV; cnt > 1; cnt >>= 1) {
+    const int half = cnt >> 1;
+    const bool hi = lane & mask;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const bool hi = lane & 16;
-    const double keep = hi ? v[8 + i] : v[i];
-    const double send = hi ? v[i] : v[8 + i];
-    v[i] = keep + __shfl_xor(send, 16, 64);
+    for (int i = 0; i < half; ++i) {
+      const double keep = hi ? v[half + i] : v[i];
+      const double send = hi ? v[i] : v[half + i];
+      v[i] = keep + __shfl_xor(send, mask, 64);
+    }
+    mask >>= 1;
   }
+  double x = v[0];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const bool hi = lane & 8;
-    const double keep = hi ? v[4 + i] : v[i];
-    const double send = hi ? v[i] : v[4 + i];
-    v[i] = keep + __shfl_xor(send, 8, 64);
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const bool hi = lane & 4;
-    const double keep = hi ? v[2 + i] : v[i];
-    const double send = hi ? v[i] : v[2 + i];
-    v[i] = keep + __shfl_xor(send, 4, 64);
-  }
-  {
-    const bool hi = lane & 2;
-    const double keep = hi ? v[1] : v[0];
-    const double send = hi ? v[0] : v[1];
-    v[0] = keep + __shfl_xor(send, 2, 64);
-  }
-  return v[0] + __shfl_xor(v[0], 1, 64);
+  for (; mask >= 1; mask >>= 1) x += __shfl_xor(x, mask, 64);
+  return x;
 }
 
-template <bool MIXED, int RG>
-__global__ __launch_bounds__(64 * RG) void k_pair_band(
+template <int NV>
+constexpr int log2_of() { return NV <= 1 ? 0 : 1 + log2_of<NV / 2>(); }
+
+// RG alive rows per work-group; each row's 8 targets are split over
+// TB / TPW waves of TPW targets each; PS samples of the target rows are
+// staged through LDS per step.
+template <bool MIXED, int RG, int TPW, int PS>
+__global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(
     const double* __restrict__ Z, int64_t ldz, int64_t n, const double* __restrict__ Sig,
     const double* __restrict__ dsc, const double* __restrict__ M,
     const uint8_t* __restrict__ alive, const int32_t* __restrict__ alive_list,
     double* __restrict__ P, uint8_t* __restrict__ pend, const int32_t* __restrict__ idx, int p,
     BandArgs a, Ctl* ctl) {
-  __shared__ double lds[TB][PSUB];   // the 8 rows of target block B, one stage
-  __shared__ uint32_t s_mask[RG];
+  constexpr int WPR = TB / TPW;     // waves per row
+  constexpr int NW = RG * WPR;      // waves per work-group
+  constexpr int SPL = PS / 64;      // samples per lane and stage
+  __shared__ double lds[TB][PS];    // the 8 rows of target block B, one stage
+  __shared__ uint32_t s_mask[NW];
   __shared__ int s_stop, s_m;
-  // XCD-aware order: consecutive logical work-groups (same chunk and target
-  // block, different row groups) land on the same XCD and share its L2
-  const int per = gridDim.x / 8;
-  const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  const int G = a.ntb * a.nchunk * a.nrg;
-  if (logical >= G) return;
-  const int g = logical % a.nrg;
-  const int tb = (logical / a.nrg) % a.ntb;
-  const int chunk = logical / (a.nrg * a.ntb);
-  const int B = a.tb0 + tb;
   // the stop decision and the alive count are read once and shared, so the
   // whole work-group decides together
   if (threadIdx.x == 0) {
@@ -462,22 +447,36 @@ __global__ __launch_bounds__(64 * RG) void k_pair_band(
   }
   __syncthreads();
   const int m = s_m;
-  if (s_stop || g * RG >= m) return;
-
+  if (s_stop) return;
+  // items (row group, target block, chunk) that exist for this alive count;
+  // the grid is bounded and each work-group walks its share of them.  Work-
+  // groups are dealt round-robin over the 8 XCDs, so each XCD takes one
+  // contiguous eighth of the items (same chunk and target block, different
+  // row groups) and its work-groups share the XCD's L2.
+  const int nrg = (m + RG - 1) / RG;
+  const int items = nrg * a.ntb * a.nchunk;
+  const int xcd = blockIdx.x % 8, per_xcd = gridDim.x / 8;
+  const int ipx = (items + 7) / 8;
+  const int lo = xcd * ipx, hi = min(items, lo + ipx);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int lane = threadIdx.x % 64;
   const int r = a.r;
-  const int q = g * RG + wave;
+  for (int item = lo + (int)(blockIdx.x / 8); item < hi; item += per_xcd) {
+  const int g = item % nrg;
+  const int tb = (item / nrg) % a.ntb;
+  const int chunk = item / (nrg * a.ntb);
+  const int B = a.tb0 + tb;
+  const int q = g * RG + wave / WPR;
+  const int j0 = (wave % WPR) * TPW;  // first target of this wave within B
   const int v = q < m ? alive_list[q] : -1;
-
-  // which of the 8 pairs (v, w in B) this wave evaluates (wave-uniform)
+  // which of the TPW pairs (v, w in B) this wave evaluates (wave-uniform)
   uint32_t mask = 0;
   if (v >= 0) {
     const int bv = v / TB;
     const bool v_in_targets = bv >= a.tb0 && bv < a.tb0 + a.ntb;
 #pragma unroll
-    for (int j = 0; j < TB; ++j) {
-      const int w = B * TB + j;
+    for (int j = 0; j < TPW; ++j) {
+      const int w = B * TB + j0 + j;
       if (w >= r || w == v) continue;
       if (!__builtin_isnan(M[(int64_t)v * p + w])) continue;
       const bool w_row = alive[w] != 0 && v_in_targets;  // w also a row of this band
@@ -487,27 +486,28 @@ __global__ __launch_bounds__(64 * RG) void k_pair_band(
   mask = __builtin_amdgcn_readfirstlane(mask);
   if (lane == 0) s_mask[wave] = mask;
   __syncthreads();
-  // waves without work end here; a barrier waits only for the waves still
-  // running, so they do not hold the work-group's slots for nothing
-  if (mask == 0) return;
   int n_act = 0, rank = 0;
 #pragma unroll
-  for (int w = 0; w < RG; ++w) {
+  for (int w = 0; w < NW; ++w) {
     if (s_mask[w]) {
       n_act += 1;
       if (w < wave) rank += 1;
     }
   }
+  if (n_act == 0) {  // nothing in this item for any wave (uniform)
+    __syncthreads();
+    continue;
+  }
 
   // per-pair regression coefficient b (correlation of the normalised rows)
   // and scale s = 1/sqrt(1 - b^2) (Eq. var_update)
-  double bj[TB], sj[TB];
+  double bj[TPW], sj[TPW];
 #pragma unroll
-  for (int j = 0; j < TB; ++j) {
+  for (int j = 0; j < TPW; ++j) {
     bj[j] = 0.0;
     sj[j] = 1.0;
     if (mask >> j & 1u) {
-      const int w = B * TB + j;
+      const int w = B * TB + j0 + j;
       const double b = Sig[(int64_t)v * p + w] * dsc[v] * dsc[w];
       const double om = 1.0 - b * b;
       if (!(om > DEGEN_EPS)) {
@@ -521,31 +521,33 @@ __global__ __launch_bounds__(64 * RG) void k_pair_band(
 
   const int64_t k0 = (int64_t)chunk * a.chunk;
   const int64_t kend = min(n, k0 + (int64_t)a.chunk);
-  const double dv = dsc[v];
-  const double* zrow = Z + (int64_t)v * ldz;
+  const double dv = mask ? dsc[v] : 0.0;
+  const double* zrow = Z + (int64_t)(mask ? v : 0) * ldz;
 
   // accumulators: [j][0] lc(r_v), [j][1] g(r_v), [j][2] lc(r_w), [j][3] g(r_w)
   using acc_t = typename std::conditional<MIXED, float, double>::type;
-  acc_t acc[TB][4];
+  acc_t acc[TPW][4];
 #pragma unroll
-  for (int j = 0; j < TB; ++j)
+  for (int j = 0; j < TPW; ++j)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[j][c] = 0;
-  float ca[TB], cg[TB];
+  float ca[TPW], cg[TPW];
 #pragma unroll
-  for (int j = 0; j < TB; ++j) {
+  for (int j = 0; j < TPW; ++j) {
     ca[j] = (float)(-2.0 * 1.4426950408889634074 * sj[j]);
     cg[j] = (float)(-0.5 * 1.4426950408889634074 * sj[j] * sj[j]);
   }
 
-  for (int64_t ks = k0; ks < kend; ks += PSUB) {
-    const int cnt = (int)min((int64_t)PSUB, kend - ks);
-    // the active waves stage the 8 rows of block B (ldz is a multiple of PSUB)
-    for (int e = rank * 64 + lane; e < TB * PSUB / 2; e += n_act * 64) {
-      const int row = e / (PSUB / 2), c2 = e % (PSUB / 2);
+  for (int64_t ks = k0; ks < kend; ks += PS) {
+    const int cnt = (int)min((int64_t)PS, kend - ks);
+    // the active waves stage the 8 rows of block B (only samples < kend are
+    // read, so every load stays inside its row)
+    if (mask)
+    for (int e = rank * 64 + lane; e < TB * PS / 2; e += n_act * 64) {
+      const int row = e / (PS / 2), c2 = e % (PS / 2);
       const int var = B * TB + row;
       double2 val = make_double2(0.0, 0.0);
-      if (var < r) {
+      if (var < r && 2 * c2 < cnt) {
         val = *reinterpret_cast<const double2*>(Z + (int64_t)var * ldz + ks + 2 * c2);
         const double d = dsc[var];
         val.x *= d;
@@ -553,17 +555,23 @@ __global__ __launch_bounds__(64 * RG) void k_pair_band(
       }
       *reinterpret_cast<double2*>(&lds[row][2 * c2]) = val;
     }
+    // this lane's samples of the own row, fetched before the barrier
+    double zv[SPL];
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) {
+      const int k = i * 64 + lane;
+      zv[i] = mask && k < cnt ? dv * zrow[ks + k] : 0.0;
+    }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < PSUB / 64; ++i) {
+    for (int i = 0; i < SPL; ++i) {
       const int k = i * 64 + lane;
-      if (k < cnt) {
-        const double zv = dv * zrow[ks + k];
+      if (mask && k < cnt) {
 #pragma unroll
-        for (int j = 0; j < TB; ++j) {
-          const double zw = lds[j][k];
-          const double rv = __builtin_fma(-bj[j], zw, zv);  // r_v^(w) / s
-          const double rw = __builtin_fma(-bj[j], zv, zw);  // r_w^(v) / s
+        for (int j = 0; j < TPW; ++j) {
+          const double zw = lds[j0 + j][k];
+          const double rv = __builtin_fma(-bj[j], zw, zv[i]);  // r_v^(w) / s
+          const double rw = __builtin_fma(-bj[j], zv[i], zw);  // r_w^(v) / s
           if constexpr (MIXED) {
             terms_mixed((float)rv, ca[j], cg[j], acc[j][0], acc[j][1]);
             terms_mixed((float)rw, ca[j], cg[j], acc[j][2], acc[j][3]);
@@ -580,9 +588,10 @@ __global__ __launch_bounds__(64 * RG) void k_pair_band(
   }
 
   // convert to sum(log cosh u + ln 2) and sum(u exp(-u^2/2)), reduce over the wave
-  double vals[32];
+  constexpr int NV = 4 * TPW;
+  double vals[NV];
 #pragma unroll
-  for (int j = 0; j < TB; ++j) {
+  for (int j = 0; j < TPW; ++j) {
     if constexpr (MIXED) {
       vals[4 * j + 0] = (double)acc[j][0] * LN2;
       vals[4 * j + 1] = (double)acc[j][1] * sj[j];
@@ -593,50 +602,56 @@ __global__ __launch_bounds__(64 * RG) void k_pair_band(
       for (int c = 0; c < 4; ++c) vals[4 * j + c] = (double)acc[j][c];
     }
   }
-  const double tot = reduce_scatter32(vals);
-  if ((lane & 1) == 0) {
-    const int qq = lane >> 1, j = qq >> 2, c = qq & 3;
+  const double tot = mask ? reduce_scatter<NV>(vals) : 0.0;
+  constexpr int SH = 6 - log2_of<NV>();
+  if ((lane & ((1 << SH) - 1)) == 0) {
+    const int qq = lane >> SH, j = qq >> 2, c = qq & 3;
     if (mask >> j & 1u) {
-      const int w = B * TB + j;
+      const int w = B * TB + j0 + j;
       P[(((int64_t)chunk * p + v) * p + w) * 4 + c] = tot;
       P[(((int64_t)chunk * p + w) * p + v) * 4 + ((c + 2) & 3)] = tot;
     }
   }
-  if (chunk == 0 && lane < TB && (mask >> lane & 1u)) {
-    const int w = B * TB + lane;
+  if (chunk == 0 && lane < TPW && (mask >> lane & 1u)) {
+    const int w = B * TB + j0 + lane;
     pend[(int64_t)v * p + w] = 1;
     pend[(int64_t)w * p + v] = 1;
   }
-  if (chunk == 0 && lane == 0) {
+  if (chunk == 0 && lane == 0 && mask) {
     atomicAdd(&ctl->pairs_evaluated, (unsigned long long)__popc(mask));
-    atomicAdd(&ctl->pairs_computed, (unsigned long long)TB);
+    atomicAdd(&ctl->pairs_computed, (unsigned long long)TPW);
+  }
+  __syncthreads();  // s_mask and lds are reused by the next item
   }
 }
 
-// Alive rows per work-group.  Large groups share each staged target block
-// among many rows (dense bands, where every variable is still alive); small
-// groups spread the few alive rows of later bands over more CUs.  The
-// grouping does not change any arithmetic.
-constexpr int RG_DENSE = 16;  // binary32 terms, <= 128 VGPRs for 16 waves per CU
-constexpr int RG_SPARSE = 4;
-
-template <bool MIXED, int RG>
-static void launch_pair_rg(const Dev& d, int buf, BandArgs a, hipStream_t s) {
+// Work-group shapes of the pair kernel (results do not depend on them).
+// Dense bands (every variable still alive): 16 rows x 8 targets per wave,
+// so each staged target block is shared by 16 rows.  Sparse bands: 4 rows,
+// each row's 8 targets split over 4 waves of 2, giving the few alive rows
+// four times as many (and shorter) waves, and 512-sample LDS stages so a
+// chunk needs only four load round trips.  The FP64 variant uses fewer
+// waves per group because its terms need more registers per lane.
+template <bool MIXED, int RG, int TPW, int PS>
+static void launch_pair_shape(const Dev& d, int buf, BandArgs a, hipStream_t s, int max_groups) {
   a.nrg = (a.r + RG - 1) / RG;
-  const int G = a.ntb * a.nchunk * a.nrg;
+  const int G = std::min(a.ntb * a.nchunk * a.nrg, max_groups);  // items when every row is alive
   const int grid = (G + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_pair_band<MIXED, RG>), dim3(grid), dim3(64 * RG), 0, s, d.Z[buf], d.ldz, d.n,
-                     d.Sig[buf], d.dsc[buf], d.M, d.alive, d.alive_list, d.P, d.pend, d.idx[buf], d.p, a,
-                     d.ctl);
+  hipLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS>), dim3(grid), dim3(64 * RG * (TB / TPW)), 0, s, d.Z[buf],
+                     d.ldz, d.n, d.Sig[buf], d.dsc[buf], d.M, d.alive, d.alive_list, d.P, d.pend, d.idx[buf],
+                     d.p, a, d.ctl);
 }
 
 hipError_t launch_pair_band(const Dev& d, int buf, const BandArgs& a, int mixed, int dense, hipStream_t s) {
+  // bounded grids: enough work-groups to fill every CU a few times over
   if (mixed && dense)
-    launch_pair_rg<true, RG_DENSE>(d, buf, a, s);
+    launch_pair_shape<true, 16, 8, 256>(d, buf, a, s, 1 << 30);
   else if (mixed)
-    launch_pair_rg<true, RG_SPARSE>(d, buf, a, s);
+    launch_pair_shape<true, 4, 2, 512>(d, buf, a, s, 1024);
+  else if (dense)
+    launch_pair_shape<false, 4, 8, 256>(d, buf, a, s, 1 << 30);
   else
-    launch_pair_rg<false, RG_SPARSE>(d, buf, a, s);  // binary64 terms need more registers per lane
+    launch_pair_shape<false, 2, 2, 512>(d, buf, a, s, 2048);
   return hipGetLastError();
 }
 
@@ -644,15 +659,17 @@ hipError_t launch_pair_band(const Dev& d, int buf, const BandArgs& a, int mixed,
 // a5/a6: tests, scores, threshold state, termination and root
 // ============================================================================
 // Rows whose tests can have changed in a band: the variables of the target
-// blocks, then the alive variables outside them.  One wave per row forms
-// the pending tests from the chunk partial sums and recomputes the row's
-// score in a fixed order.
+// blocks, then the alive variables outside them.  One work-group per row
+// forms the pending tests from the chunk partial sums and recomputes the
+// row's score in a fixed order.
 __global__ __launch_bounds__(256) void k_score(double* __restrict__ M, uint8_t* __restrict__ pend,
                                                const double* __restrict__ P, const double* __restrict__ H,
                                                double* __restrict__ S, uint8_t* __restrict__ complete,
                                                const int32_t* __restrict__ alive_list, int r, int p,
                                                int nchunk, double n, int tb0, int ntb, const Ctl* ctl) {
   __shared__ int s_stop, s_m;
+  __shared__ double sh[4];
+  __shared__ int shi[4];
   if (threadIdx.x == 0) {
     s_stop = halted(ctl) || ctl->done;
     s_m = ctl->n_alive;
@@ -660,50 +677,50 @@ __global__ __launch_bounds__(256) void k_score(double* __restrict__ M, uint8_t* 
   __syncthreads();
   if (s_stop) return;
   const int m = s_m;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int qrow = blockIdx.x * 4 + wave;
   const int t_lo = tb0 * TB, t_hi = min(r, (tb0 + ntb) * TB);
+  const int rows = (t_hi - t_lo) + m;
+  for (int qrow = blockIdx.x; qrow < rows; qrow += gridDim.x) {
   int x = -1;
   if (qrow < t_hi - t_lo) {
     x = t_lo + qrow;
-  } else if (qrow - (t_hi - t_lo) < m) {
+  } else {
     const int y = alive_list[qrow - (t_hi - t_lo)];
     if (y < t_lo || y >= t_hi) x = y;
   }
-  if (x >= 0) {
-    double s = 0.0;
-    int incomplete = 0;
-    const double hx = H[x];
-    for (int w = lane; w < r; w += 64) {
-      if (w == x) continue;
-      double mv;
-      if (pend[(int64_t)x * p + w]) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        for (int c = 0; c < nchunk; ++c) {
-          const double* q = P + (((int64_t)c * p + x) * p + w) * 4;
-          a0 += q[0]; a1 += q[1]; a2 += q[2]; a3 += q[3];
-        }
-        const double h_rx = happ_from_sums(a0, a1, n);  // H(r_x^(w))
-        const double h_rw = happ_from_sums(a2, a3, n);  // H(r_w^(x))
-        mv = (H[w] + h_rx) - (hx + h_rw);               // Eq. (Itest)
-        M[(int64_t)x * p + w] = mv;
-        pend[(int64_t)x * p + w] = 0;
-      } else {
-        mv = M[(int64_t)x * p + w];
+  if (x < 0) continue;  // uniform over the work-group
+  double s = 0.0;
+  int incomplete = 0;
+  const double hx = H[x];
+  for (int w = threadIdx.x; w < r; w += 256) {
+    if (w == x) continue;
+    double mv;
+    if (pend[(int64_t)x * p + w]) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      for (int c = 0; c < nchunk; ++c) {
+        const double* q = P + (((int64_t)c * p + x) * p + w) * 4;
+        a0 += q[0]; a1 += q[1]; a2 += q[2]; a3 += q[3];
       }
-      if (__builtin_isnan(mv)) {
-        incomplete = 1;
-      } else {
-        const double neg = mv < 0.0 ? mv : 0.0;
-        s += neg * neg;
-      }
+      const double h_rx = happ_from_sums(a0, a1, n);  // H(r_x^(w))
+      const double h_rw = happ_from_sums(a2, a3, n);  // H(r_w^(x))
+      mv = (H[w] + h_rx) - (hx + h_rw);               // Eq. (Itest)
+      M[(int64_t)x * p + w] = mv;
+      pend[(int64_t)x * p + w] = 0;
+    } else {
+      mv = M[(int64_t)x * p + w];
     }
-    s = wave_sum(s);
-    incomplete = __any(incomplete) ? 1 : 0;
-    if (lane == 0) {
-      S[x] = s;
-      complete[x] = incomplete ? 0 : 1;
+    if (__builtin_isnan(mv)) {
+      incomplete = 1;
+    } else {
+      const double neg = mv < 0.0 ? mv : 0.0;
+      s += neg * neg;
     }
+  }
+  s = block_sum256(s, sh);
+  incomplete = block_or256(incomplete, shi);
+  if (threadIdx.x == 0) {
+    S[x] = s;
+    complete[x] = incomplete ? 0 : 1;
+  }
   }
 }
 
@@ -794,8 +811,8 @@ __global__ __launch_bounds__(64) void k_decide(const double* __restrict__ S, uin
 
 hipError_t launch_score(const Dev& d, int buf, const BandArgs& a, int round_end, int t,
                         double gamma_mult, hipStream_t s) {
-  const int rows = std::min(a.r, a.ntb * TB) + a.r;
-  hipLaunchKernelGGL(k_score, dim3((rows + 3) / 4), dim3(256), 0, s, d.M, d.pend, d.P, d.H, d.S,
+  const int rows = std::min(a.r, a.ntb * TB) + a.r;  // rows when every variable is alive
+  hipLaunchKernelGGL(k_score, dim3(std::min(rows, 512)), dim3(256), 0, s, d.M, d.pend, d.P, d.H, d.S,
                      d.complete, d.alive_list, a.r, d.p, a.nchunk, (double)d.n, a.tb0, a.ntb, d.ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

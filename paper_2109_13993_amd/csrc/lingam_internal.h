@@ -15,9 +15,7 @@ constexpr int PAIR_THREADS = 64 * PAIR_WAVES;
 // Row stride unit of the stored data (doubles); every sample range a kernel
 // stages starts at a multiple of it.
 constexpr int SUB = 256;
-// Samples of the 8 target rows staged through LDS per step of the pair
-// kernel (8 x PSUB doubles = 8 KiB).
-constexpr int PSUB = 128;
+
 // Samples per work-group chunk: at most 32 per lane, so the binary32 lane
 // sums of the mixed mode never run over more than 32 terms.
 constexpr int CHUNK_DEFAULT = 2048;
