@@ -408,8 +408,10 @@ __device__ __forceinline__ double reduce_scatter(double (&v)[NV]) {
     const bool hi = lane & mask;
 #pragma unroll
     for (int i = 0; i < half; ++i) {
-      const double keep = hi ? v[half + i] : v[i];
-      const double send = hi ? v[i] : v[half + i];
+      // select values, not array slots, so that v stays in registers
+      const double lo_v = v[i], hi_v = v[half + i];
+      const double keep = hi ? hi_v : lo_v;
+      const double send = hi ? lo_v : hi_v;
       v[i] = keep + __shfl_xor(send, mask, 64);
     }
     mask >>= 1;
