@@ -53,14 +53,51 @@ def measured_traffic():
 
 
 def timed_runs(lg, X, precision, steps, warmup, **kw):
+    """Wall time per search over `steps` searches (after `warmup`), then the
+    same number of searches again with every pair-kernel launch bracketed by
+    HIP events on the library's stream (the event records add a little time,
+    so those searches give the kernel durations, not the wall time)."""
     import torch
     for _ in range(warmup):
         lg.fit_order(X, precision=precision, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = [lg.fit_order(X, precision=precision, profile=True, **kw) for _ in range(steps)]
+    res = [lg.fit_order(X, precision=precision, **kw) for _ in range(steps)]
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps, res
+    t_plain = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    prof = [lg.fit_order(X, precision=precision, profile=True, **kw) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t_prof = (time.perf_counter() - t0) / steps
+    return t_plain, res, t_prof, prof
+
+
+def mixed_error_report(rm, r64, p):
+    """Score error of the mixed run against the FP64 run over the iterations
+    both share (same prefix of the order), the a-priori bounds, and the gap
+    rule: iterations whose top score is separated from every other by the
+    bounds, and how many of those disagree with FP64 (must be 0)."""
+    import numpy as np
+    diff = np.flatnonzero(rm.order != r64.order)
+    upto = int(diff[0]) + 1 if diff.size else p - 1
+    upto = min(upto, p - 1)
+    both = (rm.T_state[:upto] == 1) & (r64.T_state[:upto] == 1)
+    dT = np.abs(rm.T[:upto][both] - r64.T[:upto][both])
+    certified = violations = 0
+    for t in range(upto):
+        row, err = rm.T[t], rm.T_err[t]
+        live = np.isfinite(row)
+        comp = live & (rm.T_state[t] == 1)
+        top = int(np.flatnonzero(comp)[np.argmax(row[comp])])
+        others = live.copy()
+        others[top] = False
+        if not others.any() or row[top] - err[top] > np.max(row[others] + err[others]):
+            certified += 1
+            violations += int(top != r64.order[t])
+    return {"iterations_compared": upto, "max_abs_dT": float(dT.max()) if dT.size else 0.0,
+            "max_T_err_bound": float(np.nanmax(rm.T_err[:upto][both])) if dT.size else 0.0,
+            "max_dT_over_bound": float(np.max(dT / (rm.T_err[:upto][both] + 1e-12))) if dT.size else 0.0,
+            "gap_rule_certified_iterations": certified, "gap_rule_violations": violations}
 
 
 def cpu_baseline(X, nvars):
@@ -80,7 +117,7 @@ def cpu_baseline(X, nvars):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 searches (default: --steps)")
     ap.add_argument("--cpu-vars", type=int, default=160, help="variables in the CPU-oracle sample")
@@ -116,11 +153,11 @@ def main():
     torch.cuda.synchronize()
     log("workload p=%d n=%d on %s" % (p, n, torch.cuda.get_device_name(0)))
 
-    t_mix, res_mix = timed_runs(lg, X, "mixed", args.steps, args.warmup)
+    t_mix, res_mix, t_mix_prof, prof_mix = timed_runs(lg, X, "mixed", args.steps, args.warmup)
     pairs = res_mix[-1].pair_samples
     value = pairs / t_mix
-    kern_s = sum(r.seconds_pair_kernel for r in res_mix) / len(res_mix)
-    launches = res_mix[-1].pair_kernel_launches
+    kern_s = sum(r.seconds_pair_kernel for r in prof_mix) / len(prof_mix)
+    launches = prof_mix[-1].pair_kernel_launches
     achieved = pairs * SLOTS_PER_PAIR_SAMPLE_MIXED / kern_s
     log("mixed: %.1f ms/search, %.3e pair-samples/s, pair kernel %.1f ms in %d launches "
         "(%.1f us avg), pairs %d evaluated / %d computed" % (
@@ -146,19 +183,22 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
                      "unit": "Tlane-slot/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": measured_traffic(),
                      "kernel": "k_pair_band<mixed>", "slots_per_pair_sample": SLOTS_PER_PAIR_SAMPLE_MIXED,
-                     "pair_kernel_ms_per_step": kern_s * 1e3, "launches_per_step": launches},
+                     "pair_kernel_ms_per_step": kern_s * 1e3, "launches_per_step": launches,
+                     "avg_launch_us": kern_s / max(launches, 1) * 1e6,
+                     "ms_per_step_with_events": t_mix_prof * 1e3},
         "pairs_evaluated": res_mix[-1].pairs_evaluated,
         "pairs_computed": res_mix[-1].pairs_computed,
         "effective_pair_samples_per_s": (p + 1) * p * (p - 1) // 6 * n / t_mix,
         "threshold_rounds": res_mix[-1].threshold_rounds,
     }
     if not args.no_fp64:
-        steps64 = args.fp64_steps if args.fp64_steps is not None else args.steps
-        t64, res64 = timed_runs(lg, X, "fp64", steps64, min(args.warmup, 1))
+        steps64 = args.fp64_steps if args.fp64_steps is not None else min(args.steps, 3)
+        t64, res64, _, prof64 = timed_runs(lg, X, "fp64", steps64, min(args.warmup, 1))
         v64 = res64[-1].pair_samples / t64
-        k64 = sum(r.seconds_pair_kernel for r in res64) / len(res64)
+        k64 = sum(r.seconds_pair_kernel for r in prof64) / len(prof64)
         same = bool(np.array_equal(res64[-1].order, res_mix[-1].order))
         first_diff = int(np.argmax(res64[-1].order != res_mix[-1].order)) if not same else -1
+        out["mixed_error"] = mixed_error_report(res_mix[-1], res64[-1], p)
         out["fp64"] = {"value": v64, "ms_per_step": t64 * 1e3, "pair_kernel_ms_per_step": k64 * 1e3,
                        "pairs_evaluated": res64[-1].pairs_evaluated}
         out["speedup_fp32_vs_fp64"] = t64 / t_mix

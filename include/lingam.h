@@ -99,6 +99,11 @@ typedef struct lingam_result {
   double* H;            /* [p*p]: H[t*p + v] = entropy estimate of variable v at iteration t */
   double* M;            /* [record_M_iters*p*p]: M[t*p*p + i*p + j] = I(x_i, x_j, ...) at
                            iteration t; NaN where not evaluated */
+  double* T_err_bound;  /* [p*p], MIXED precision: a-priori bound on |T - T_exact| of the
+                           entry T[t*p + v] from binary32 rounding (per-sample terms, hardware
+                           exp2/log2, lane sums), given the same data; 0 in FP64 mode, NaN
+                           where T is NaN.  When the two largest T of an iteration differ by
+                           more than the sum of their bounds, the root is the exact one. */
   uint64_t pairs_evaluated;   /* unordered pairs whose test was needed and evaluated */
   uint64_t pair_samples;      /* pairs_evaluated x n (the throughput unit) */
   uint64_t pairs_computed;    /* pairs actually run by the kernel (>= pairs_evaluated) */

@@ -58,6 +58,7 @@ class LingamResult(ctypes.Structure):
         ("T_state", ctypes.POINTER(ctypes.c_uint8)),
         ("H", ctypes.POINTER(ctypes.c_double)),
         ("M", ctypes.POINTER(ctypes.c_double)),
+        ("T_err_bound", ctypes.POINTER(ctypes.c_double)),
         ("pairs_evaluated", ctypes.c_uint64),
         ("pair_samples", ctypes.c_uint64),
         ("pairs_computed", ctypes.c_uint64),
@@ -127,6 +128,7 @@ class FitResult:
     T_state: Optional[np.ndarray] = None  # [p, p] uint8 (0 absent, 1 complete, 2 pruned)
     H: Optional[np.ndarray] = None    # [p, p] entropy of v at iteration t
     M: Optional[np.ndarray] = None    # [k, p, p] test matrices of the first k iterations
+    T_err: Optional[np.ndarray] = None  # [p, p] rounding bound of T (mixed; 0 in FP64 mode)
     pairs_evaluated: int = 0
     pair_samples: int = 0
     pairs_computed: int = 0
@@ -220,6 +222,7 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
     T = np.full((p, p), np.nan) if want_T else None
     Ts = np.zeros((p, p), dtype=np.uint8) if want_T else None
     H = np.full((p, p), np.nan) if want_H else None
+    Terr = np.full((p, p), np.nan) if want_T else None
     M = np.full((record_M_iters, p, p), np.nan) if record_M_iters > 0 else None
     res = LingamResult()
     res.order = order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
@@ -228,13 +231,15 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
         res.T_state = Ts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     if H is not None:
         res.H = H.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if Terr is not None:
+        res.T_err_bound = Terr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     if M is not None:
         res.M = M.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     st = lib.lingam_fit_order(ctypes.c_void_p(ptr), n, p, ctypes.byref(o), ctypes.byref(res))
     del host_ref, keep
     if st != OK:
         raise LingamError(st, lib.lingam_last_error().decode(), res.bad_i, res.bad_j)
-    return FitResult(order=order, T=T, T_state=Ts, H=H, M=M,
+    return FitResult(order=order, T=T, T_state=Ts, H=H, M=M, T_err=Terr,
                      pairs_evaluated=res.pairs_evaluated, pair_samples=res.pair_samples,
                      pairs_computed=res.pairs_computed, threshold_rounds=res.threshold_rounds,
                      bands=res.bands, seconds_total=res.seconds_total,

@@ -146,6 +146,7 @@ void reset_result(lingam_result* out, int64_t p, int rec) {
   if (out->T_state) std::memset(out->T_state, 0, (size_t)(p * p));
   if (out->H) for (int64_t k = 0; k < p * p; ++k) out->H[k] = NAN;
   if (out->M) for (int64_t k = 0; k < (int64_t)rec * p * p; ++k) out->M[k] = NAN;
+  if (out->T_err_bound) for (int64_t k = 0; k < p * p; ++k) out->T_err_bound[k] = NAN;
   out->pairs_evaluated = out->pair_samples = out->pairs_computed = 0;
   out->threshold_rounds = out->bands = 0;
   out->seconds_total = out->seconds_device = out->seconds_pair_kernel = 0.0;
@@ -210,11 +211,11 @@ struct Fit {
         auto bands = round0_bands(r, pl, threshold);
         for (size_t b = 0; b < bands.size(); ++b) {
           pair(buf, bands[b], b == 0);  // the first band still has every variable alive
-          HIPCHK(launch_score(d, buf, bands[b], b + 1 == bands.size() ? 1 : 0, t, gmult, s));
+          HIPCHK(launch_score(d, buf, bands[b], b + 1 == bands.size() ? 1 : 0, t, gmult, b == 0 ? 1 : 0, s));
         }
       } else {
         pair(buf, full_band(r, pl));
-        HIPCHK(launch_score(d, buf, full_band(r, pl), 1, t, gmult, s));
+        HIPCHK(launch_score(d, buf, full_band(r, pl), 1, t, gmult, 0, s));
       }
     }
   }
@@ -300,6 +301,7 @@ uint64_t lingam_workspace_size(int64_t n, int64_t p, const lingam_opts* o) {
   b += 4 * P * 8 + 2 * P;               // H, S, stats, alive/complete
   b += 16 * pp * 8 + 2 * P * 8;         // split-Gram partials, row scales
   b += pp * (8 + 1 + 8) + P * 4;        // T, T_state, H record, order
+  b += 2 * pp * 8 + 2 * P * 8;          // rounding bounds: per test, per score record, eH, eT
   b += (uint64_t)op.record_M_iters * pp * 8;
   if (!op.x_on_device) b += P * (uint64_t)n * (op.x_dtype == 1 ? 4 : 8);
   b += sizeof(Ctl);
@@ -353,7 +355,12 @@ lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam
     d.dsc[1] = al.get<double>(P);
     d.idx[0] = al.get<int32_t>(P);
     d.idx[1] = al.get<int32_t>(P);
+    d.mixed = f.mixed ? 1 : 0;
     d.H = al.get<double>(P);
+    d.eH = al.get<double>(P);
+    d.eT = al.get<double>(P);
+    d.Meps = al.get<double>(pp);
+    d.Terr = al.get<double>(pp);
     d.M = al.get<double>(pp);
     d.S = al.get<double>(P);
     d.alive = al.get<uint8_t>(P);
@@ -404,6 +411,7 @@ lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam
     HIPCHK(launch_fill(d.Tall, (int64_t)pp, NAN, f.s));
     HIPCHK(launch_fill_u8(d.Tstate, (int64_t)pp, 0, f.s));
     HIPCHK(launch_fill(d.Hall, (int64_t)pp, NAN, f.s));
+    HIPCHK(launch_fill(d.Terr, (int64_t)pp, NAN, f.s));
     if (d.Mrec) HIPCHK(launch_fill(d.Mrec, (int64_t)d.rec * (int64_t)pp, NAN, f.s));
     HIPCHK(launch_fill_u8(reinterpret_cast<uint8_t*>(d.order), (int64_t)(4 * P), 0xff, f.s));
 
@@ -437,7 +445,7 @@ lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam
         HIPCHK(launch_resume(d, f.s));
         for (int extra = 0;; ++extra) {
           f.pair(buf, full_band(rf, f.pl));
-          HIPCHK(launch_score(d, buf, full_band(rf, f.pl), 1, tf, f.gmult, f.s));
+          HIPCHK(launch_score(d, buf, full_band(rf, f.pl), 1, tf, f.gmult, 0, f.s));
           c = f.read_ctl();
           if (c.status != ST_OK || c.done) break;
           if (extra > rf + 8) throw HipFail{hipErrorUnknown, "threshold rounds did not terminate", __LINE__};
@@ -456,6 +464,8 @@ lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam
     if (out->T) HIPCHK(hipMemcpyAsync(out->T, d.Tall, sizeof(double) * pp, hipMemcpyDeviceToHost, f.s));
     if (out->T_state) HIPCHK(hipMemcpyAsync(out->T_state, d.Tstate, pp, hipMemcpyDeviceToHost, f.s));
     if (out->H) HIPCHK(hipMemcpyAsync(out->H, d.Hall, sizeof(double) * pp, hipMemcpyDeviceToHost, f.s));
+    if (out->T_err_bound)
+      HIPCHK(hipMemcpyAsync(out->T_err_bound, d.Terr, sizeof(double) * pp, hipMemcpyDeviceToHost, f.s));
     if (out->M && d.rec > 0)
       HIPCHK(hipMemcpyAsync(out->M, d.Mrec, sizeof(double) * pp * d.rec, hipMemcpyDeviceToHost, f.s));
     HIPCHK(hipStreamSynchronize(f.s));

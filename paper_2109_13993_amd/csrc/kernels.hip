@@ -25,6 +25,7 @@
 #include "lingam_internal.h"
 
 #include <algorithm>
+#include <atomic>
 
 #include <cmath>
 #include <type_traits>
@@ -103,6 +104,30 @@ __device__ __forceinline__ void terms_mixed(float x, float ca, float cg, float& 
   const float t = x * cg;
   const float e2 = __builtin_amdgcn_exp2f(t * x);
   g = __builtin_fmaf(x, e2, g);
+}
+
+// A-priori rounding bound of one entropy estimate of the mixed mode, from
+// its sums s_lc = sum (log cosh u + ln 2) and s_g = sum u exp(-u^2/2) over n
+// samples of a unit-variance u (so mean |u| <= 1).  With u32 = 2^-24 and the
+// hardware exp2 / log2 taken within 4 u32 relative / 8 u32 absolute:
+//   per term of log cosh: residual and scale rounding (3 u32 on the exp2
+//   argument, slope <= 1/2) 4.33 u32 |u|, exp2 + add + log2 12.33 u32, the
+//   fma u32 |t|; binary32 lane sums of <= 32 terms add 31 u32 sum |t|, so in
+//   natural units  dE1 <= u32 (32 s_lc / n + ln 2 (4.33 + 12.33));
+//   per term of u exp(-u^2/2): 5 u32 |g| + 2.5 u32 |u|^3 exp(-u^2/2) <= 5.93 u32,
+//   lane sums 32 u32 sum |g| with |g| <= exp(-1/2):  dE2 <= 25.4 u32.
+// Eq. (HApp) then moves by at most
+//   2 k1 |E1 - beta| dE1 + 3 k1 dE1^2 + 2 k2 |E2| dE2 + 3 k2 dE2^2
+// (E1, E2 the computed means; the factor 3 absorbs using them in place of the
+// exact ones).
+__device__ __forceinline__ double happ_err_mixed(double s_lc, double s_g, double n) {
+  constexpr double U32 = 5.9604644775390625e-08;
+  const double E1 = s_lc / n - LN2;
+  const double E2 = s_g / n;
+  const double d1 = U32 * (32.0 * (s_lc / n) + 11.6);
+  const double d2 = U32 * 25.4;
+  return 2.0 * K1 * fabs(E1 - BETA) * d1 + 3.0 * K1 * d1 * d1 + 2.0 * K2 * fabs(E2) * d2 +
+         3.0 * K2 * d2 * d2;
 }
 
 __device__ __forceinline__ double happ_from_sums(double s_lc, double s_g, double n) {
@@ -304,7 +329,8 @@ hipError_t launch_gram(const Dev& d, int buf, int r, hipStream_t s) {
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_entropy(const double* __restrict__ Z, int64_t ldz, int64_t n,
                                                  const double* __restrict__ dsc,
-                                                 double* __restrict__ H, const Ctl* ctl) {
+                                                 double* __restrict__ H, double* __restrict__ eH,
+                                                 const Ctl* ctl) {
   if (halted(ctl)) return;
   __shared__ double sh[4];
   const double* z = Z + (int64_t)blockIdx.x * ldz;
@@ -324,14 +350,18 @@ __global__ __launch_bounds__(256) void k_entropy(const double* __restrict__ Z, i
   }
   lc = block_sum256(lc, sh);
   g = block_sum256(g, sh);
-  if (threadIdx.x == 0) H[blockIdx.x] = happ_from_sums(lc, g, (double)n);
+  if (threadIdx.x == 0) {
+    H[blockIdx.x] = happ_from_sums(lc, g, (double)n);
+    eH[blockIdx.x] = MIXED ? happ_err_mixed(lc, g, (double)n) : 0.0;
+  }
 }
 
 hipError_t launch_entropy(const Dev& d, int buf, int r, int mixed, hipStream_t s) {
   if (mixed)
-    hipLaunchKernelGGL(k_entropy<true>, dim3(r), dim3(256), 0, s, d.Z[buf], d.ldz, d.n, d.dsc[buf], d.H, d.ctl);
+    hipLaunchKernelGGL(k_entropy<true>, dim3(r), dim3(256), 0, s, d.Z[buf], d.ldz, d.n, d.dsc[buf], d.H, d.eH, d.ctl);
   else
-    hipLaunchKernelGGL(k_entropy<false>, dim3(r), dim3(256), 0, s, d.Z[buf], d.ldz, d.n, d.dsc[buf], d.H, d.ctl);
+    hipLaunchKernelGGL(k_entropy<false>, dim3(r), dim3(256), 0, s, d.Z[buf], d.ldz, d.n, d.dsc[buf], d.H, d.eH,
+                       d.ctl);
   return hipGetLastError();
 }
 
@@ -426,8 +456,10 @@ template <int NV>
 constexpr int log2_of() { return NV <= 1 ? 0 : 1 + log2_of<NV / 2>(); }
 
 // RG alive rows per work-group; each row's 8 targets are split over
-// TB / TPW waves of TPW targets each; PS samples of the target rows are
-// staged through LDS per step.
+// TB / TPW waves of TPW targets each.  The 8 target rows are staged through
+// LDS PS samples at a time, double-buffered: the loads of the next stage are
+// issued before the current stage is computed, so one barrier per stage
+// suffices and the load latency hides behind the arithmetic.
 template <bool MIXED, int RG, int TPW, int PS>
 __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(
     const double* __restrict__ Z, int64_t ldz, int64_t n, const double* __restrict__ Sig,
@@ -438,7 +470,11 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(
   constexpr int WPR = TB / TPW;     // waves per row
   constexpr int NW = RG * WPR;      // waves per work-group
   constexpr int SPL = PS / 64;      // samples per lane and stage
-  __shared__ double lds[TB][PS];    // the 8 rows of target block B, one stage
+  constexpr int NT = 64 * NW;       // threads
+  constexpr int NSTG = TB * PS / 2 / NT;  // double2 of the target rows each thread stages
+  static_assert(NSTG >= 1 && NSTG * NT == TB * PS / 2, "stage must split evenly over the threads");
+  __shared__ double lds[2][TB][PS];  // the 8 rows of target block B, two stages
+  __shared__ double s_sc[NW][TPW];   // per-pair scale s = 1/sqrt(1 - b^2)
   __shared__ uint32_t s_mask[NW];
   __shared__ int s_stop, s_m;
   // the stop decision and the alive count are read once and shared, so the
@@ -488,26 +524,23 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(
   mask = __builtin_amdgcn_readfirstlane(mask);
   if (lane == 0) s_mask[wave] = mask;
   __syncthreads();
-  int n_act = 0, rank = 0;
+  int n_act = 0;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    if (s_mask[w]) {
-      n_act += 1;
-      if (w < wave) rank += 1;
-    }
-  }
+  for (int w = 0; w < NW; ++w) n_act += s_mask[w] ? 1 : 0;
   if (n_act == 0) {  // nothing in this item for any wave (uniform)
     __syncthreads();
     continue;
   }
 
   // per-pair regression coefficient b (correlation of the normalised rows)
-  // and scale s = 1/sqrt(1 - b^2) (Eq. var_update)
-  double bj[TPW], sj[TPW];
+  // and scale s = 1/sqrt(1 - b^2) (Eq. var_update); s waits in LDS for the
+  // epilogue so it holds no registers during the sample loop
+  double bj[TPW];
+  float ca[TPW], cg[TPW];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     bj[j] = 0.0;
-    sj[j] = 1.0;
+    double sj = 1.0;
     if (mask >> j & 1u) {
       const int w = B * TB + j0 + j;
       const double b = Sig[(int64_t)v * p + w] * dsc[v] * dsc[w];
@@ -516,15 +549,47 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(
         if (lane == 0) raise_error(ctl, ST_DEGENERATE, idx[v], idx[w]);
       } else {
         bj[j] = b;
-        sj[j] = 1.0 / sqrt(om);
+        sj = 1.0 / sqrt(om);
       }
     }
+    if (lane == j) s_sc[wave][j] = sj;
+    ca[j] = (float)(-2.0 * 1.4426950408889634074 * sj);
+    cg[j] = (float)(-0.5 * 1.4426950408889634074 * sj * sj);
   }
 
   const int64_t k0 = (int64_t)chunk * a.chunk;
   const int64_t kend = min(n, k0 + (int64_t)a.chunk);
+  const int nst = (int)((kend - k0 + PS - 1) / PS);
   const double dv = mask ? dsc[v] : 0.0;
   const double* zrow = Z + (int64_t)(mask ? v : 0) * ldz;
+  // this thread's share of the staged target rows: fixed rows, so their
+  // scales are loaded once
+  double dB[NSTG];
+#pragma unroll
+  for (int i = 0; i < NSTG; ++i) {
+    const int var = B * TB + (i * NT + (int)threadIdx.x) / (PS / 2);
+    dB[i] = var < r ? dsc[var] : 0.0;
+  }
+  double2 stg[NSTG];
+  double zn[SPL];
+  // global loads of one stage into registers (only samples < kend are read,
+  // so every load stays inside its row)
+  auto load_stage = [&](int64_t ks) {
+    const int cnt = (int)min((int64_t)PS, kend - ks);
+#pragma unroll
+    for (int i = 0; i < NSTG; ++i) {
+      const int e = i * NT + (int)threadIdx.x;
+      const int row = e / (PS / 2), c2 = e % (PS / 2);
+      const int var = B * TB + row;
+      stg[i] = make_double2(0.0, 0.0);
+      if (var < r && 2 * c2 < cnt) stg[i] = *reinterpret_cast<const double2*>(Z + (int64_t)var * ldz + ks + 2 * c2);
+    }
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) {
+      const int k = i * 64 + lane;
+      zn[i] = mask && k < cnt ? zrow[ks + k] : 0.0;
+    }
+  };
 
   // accumulators: [j][0] lc(r_v), [j][1] g(r_v), [j][2] lc(r_w), [j][3] g(r_w)
   using acc_t = typename std::conditional<MIXED, float, double>::type;
@@ -533,60 +598,49 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(
   for (int j = 0; j < TPW; ++j)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[j][c] = 0;
-  float ca[TPW], cg[TPW];
-#pragma unroll
-  for (int j = 0; j < TPW; ++j) {
-    ca[j] = (float)(-2.0 * 1.4426950408889634074 * sj[j]);
-    cg[j] = (float)(-0.5 * 1.4426950408889634074 * sj[j] * sj[j]);
-  }
 
-  for (int64_t ks = k0; ks < kend; ks += PS) {
+  load_stage(k0);
+  for (int st = 0; st < nst; ++st) {
+    const int64_t ks = k0 + (int64_t)st * PS;
     const int cnt = (int)min((int64_t)PS, kend - ks);
-    // the active waves stage the 8 rows of block B (only samples < kend are
-    // read, so every load stays inside its row)
-    if (mask)
-    for (int e = rank * 64 + lane; e < TB * PS / 2; e += n_act * 64) {
+    double (*buf)[PS] = lds[st & 1];
+#pragma unroll
+    for (int i = 0; i < NSTG; ++i) {
+      const int e = i * NT + (int)threadIdx.x;
       const int row = e / (PS / 2), c2 = e % (PS / 2);
-      const int var = B * TB + row;
-      double2 val = make_double2(0.0, 0.0);
-      if (var < r && 2 * c2 < cnt) {
-        val = *reinterpret_cast<const double2*>(Z + (int64_t)var * ldz + ks + 2 * c2);
-        const double d = dsc[var];
-        val.x *= d;
-        val.y *= d;
-      }
-      *reinterpret_cast<double2*>(&lds[row][2 * c2]) = val;
+      *reinterpret_cast<double2*>(&buf[row][2 * c2]) = make_double2(stg[i].x * dB[i], stg[i].y * dB[i]);
     }
-    // this lane's samples of the own row, fetched before the barrier
     double zv[SPL];
 #pragma unroll
-    for (int i = 0; i < SPL; ++i) {
-      const int k = i * 64 + lane;
-      zv[i] = mask && k < cnt ? dv * zrow[ks + k] : 0.0;
-    }
+    for (int i = 0; i < SPL; ++i) zv[i] = dv * zn[i];
+    // buf is complete, and every wave has finished the stage that last used
+    // the other buffer
     __syncthreads();
+    if (st + 1 < nst) load_stage(ks + PS);
+    if (mask) {
 #pragma unroll
-    for (int i = 0; i < SPL; ++i) {
-      const int k = i * 64 + lane;
-      if (mask && k < cnt) {
+      for (int i = 0; i < SPL; ++i) {
+        const int k = i * 64 + lane;
+        if (k < cnt) {
 #pragma unroll
-        for (int j = 0; j < TPW; ++j) {
-          const double zw = lds[j0 + j][k];
-          const double rv = __builtin_fma(-bj[j], zw, zv[i]);  // r_v^(w) / s
-          const double rw = __builtin_fma(-bj[j], zv[i], zw);  // r_w^(v) / s
-          if constexpr (MIXED) {
-            terms_mixed((float)rv, ca[j], cg[j], acc[j][0], acc[j][1]);
-            terms_mixed((float)rw, ca[j], cg[j], acc[j][2], acc[j][3]);
-          } else {
-            double t0 = acc[j][0], t1 = acc[j][1], t2 = acc[j][2], t3 = acc[j][3];
-            terms_f64(sj[j] * rv, t0, t1);
-            terms_f64(sj[j] * rw, t2, t3);
-            acc[j][0] = t0; acc[j][1] = t1; acc[j][2] = t2; acc[j][3] = t3;
+          for (int j = 0; j < TPW; ++j) {
+            const double zw = buf[j0 + j][k];
+            const double rv = __builtin_fma(-bj[j], zw, zv[i]);  // r_v^(w) / s
+            const double rw = __builtin_fma(-bj[j], zv[i], zw);  // r_w^(v) / s
+            if constexpr (MIXED) {
+              terms_mixed((float)rv, ca[j], cg[j], acc[j][0], acc[j][1]);
+              terms_mixed((float)rw, ca[j], cg[j], acc[j][2], acc[j][3]);
+            } else {
+              const double sj = s_sc[wave][j];
+              double t0 = acc[j][0], t1 = acc[j][1], t2 = acc[j][2], t3 = acc[j][3];
+              terms_f64(sj * rv, t0, t1);
+              terms_f64(sj * rw, t2, t3);
+              acc[j][0] = t0; acc[j][1] = t1; acc[j][2] = t2; acc[j][3] = t3;
+            }
           }
         }
       }
     }
-    __syncthreads();
   }
 
   // convert to sum(log cosh u + ln 2) and sum(u exp(-u^2/2)), reduce over the wave
@@ -595,10 +649,11 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     if constexpr (MIXED) {
+      const double sj = s_sc[wave][j];
       vals[4 * j + 0] = (double)acc[j][0] * LN2;
-      vals[4 * j + 1] = (double)acc[j][1] * sj[j];
+      vals[4 * j + 1] = (double)acc[j][1] * sj;
       vals[4 * j + 2] = (double)acc[j][2] * LN2;
-      vals[4 * j + 3] = (double)acc[j][3] * sj[j];
+      vals[4 * j + 3] = (double)acc[j][3] * sj;
     } else {
 #pragma unroll
       for (int c = 0; c < 4; ++c) vals[4 * j + c] = (double)acc[j][c];
@@ -623,7 +678,7 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(
     atomicAdd(&ctl->pairs_evaluated, (unsigned long long)__popc(mask));
     atomicAdd(&ctl->pairs_computed, (unsigned long long)TPW);
   }
-  __syncthreads();  // s_mask and lds are reused by the next item
+  __syncthreads();  // s_mask, s_sc and lds are reused by the next item
   }
 }
 
@@ -634,10 +689,32 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(
 // four times as many (and shorter) waves, and 512-sample LDS stages so a
 // chunk needs only four load round trips.  The FP64 variant uses fewer
 // waves per group because its terms need more registers per lane.
+// Work-groups of one shape that the device holds at once (all CUs).
 template <bool MIXED, int RG, int TPW, int PS>
-static void launch_pair_shape(const Dev& d, int buf, BandArgs a, hipStream_t s, int max_groups) {
+static int resident_groups() {
+  static std::atomic<int> cached{0};
+  if (cached.load() == 0) {
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pair_band<MIXED, RG, TPW, PS>,
+                                                     64 * RG * (TB / TPW), 0) != hipSuccess ||
+        per_cu < 1 || cus < 1) {
+      per_cu = 1;
+      cus = 256;
+    }
+    cached.store(per_cu * cus);
+  }
+  return cached.load();
+}
+
+template <bool MIXED, int RG, int TPW, int PS>
+static void launch_pair_shape(const Dev& d, int buf, BandArgs a, hipStream_t s, int max_waves) {
   a.nrg = (a.r + RG - 1) / RG;
-  const int G = std::min(a.ntb * a.nchunk * a.nrg, max_groups);  // items when every row is alive
+  // at most max_waves generations of resident work-groups; sparse bands use
+  // one, so no work-group waits for a slot only to find nothing to do
+  const int cap = std::max(8, max_waves * resident_groups<MIXED, RG, TPW, PS>());
+  const int G = std::min(a.ntb * a.nchunk * a.nrg, cap);  // items when every row is alive
   const int grid = (G + 7) / 8 * 8;
   hipLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS>), dim3(grid), dim3(64 * RG * (TB / TPW)), 0, s, d.Z[buf],
                      d.ldz, d.n, d.Sig[buf], d.dsc[buf], d.M, d.alive, d.alive_list, d.P, d.pend, d.idx[buf],
@@ -647,96 +724,28 @@ static void launch_pair_shape(const Dev& d, int buf, BandArgs a, hipStream_t s, 
 hipError_t launch_pair_band(const Dev& d, int buf, const BandArgs& a, int mixed, int dense, hipStream_t s) {
   // bounded grids: enough work-groups to fill every CU a few times over
   if (mixed && dense)
-    launch_pair_shape<true, 16, 8, 256>(d, buf, a, s, 1 << 30);
+    launch_pair_shape<true, 16, 8, 256>(d, buf, a, s, 1 << 16);
   else if (mixed)
-    launch_pair_shape<true, 4, 2, 512>(d, buf, a, s, 1024);
+    launch_pair_shape<true, 4, 2, 512>(d, buf, a, s, 1);
   else if (dense)
-    launch_pair_shape<false, 4, 8, 256>(d, buf, a, s, 1 << 30);
+    launch_pair_shape<false, 4, 8, 256>(d, buf, a, s, 1 << 16);
   else
-    launch_pair_shape<false, 2, 2, 512>(d, buf, a, s, 2048);
+    launch_pair_shape<false, 2, 2, 512>(d, buf, a, s, 1);
   return hipGetLastError();
 }
 
 // ============================================================================
 // a5/a6: tests, scores, threshold state, termination and root
 // ============================================================================
-// Rows whose tests can have changed in a band: the variables of the target
-// blocks, then the alive variables outside them.  One work-group per row
-// forms the pending tests from the chunk partial sums and recomputes the
-// row's score in a fixed order.
-__global__ __launch_bounds__(256) void k_score(double* __restrict__ M, uint8_t* __restrict__ pend,
-                                               const double* __restrict__ P, const double* __restrict__ H,
-                                               double* __restrict__ S, uint8_t* __restrict__ complete,
-                                               const int32_t* __restrict__ alive_list, int r, int p,
-                                               int nchunk, double n, int tb0, int ntb, const Ctl* ctl) {
-  __shared__ int s_stop, s_m;
-  __shared__ double sh[4];
-  __shared__ int shi[4];
-  if (threadIdx.x == 0) {
-    s_stop = halted(ctl) || ctl->done;
-    s_m = ctl->n_alive;
-  }
-  __syncthreads();
-  if (s_stop) return;
-  const int m = s_m;
-  const int t_lo = tb0 * TB, t_hi = min(r, (tb0 + ntb) * TB);
-  const int rows = (t_hi - t_lo) + m;
-  for (int qrow = blockIdx.x; qrow < rows; qrow += gridDim.x) {
-  int x = -1;
-  if (qrow < t_hi - t_lo) {
-    x = t_lo + qrow;
-  } else {
-    const int y = alive_list[qrow - (t_hi - t_lo)];
-    if (y < t_lo || y >= t_hi) x = y;
-  }
-  if (x < 0) continue;  // uniform over the work-group
-  double s = 0.0;
-  int incomplete = 0;
-  const double hx = H[x];
-  for (int w = threadIdx.x; w < r; w += 256) {
-    if (w == x) continue;
-    double mv;
-    if (pend[(int64_t)x * p + w]) {
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      for (int c = 0; c < nchunk; ++c) {
-        const double* q = P + (((int64_t)c * p + x) * p + w) * 4;
-        a0 += q[0]; a1 += q[1]; a2 += q[2]; a3 += q[3];
-      }
-      const double h_rx = happ_from_sums(a0, a1, n);  // H(r_x^(w))
-      const double h_rw = happ_from_sums(a2, a3, n);  // H(r_w^(x))
-      mv = (H[w] + h_rx) - (hx + h_rw);               // Eq. (Itest)
-      M[(int64_t)x * p + w] = mv;
-      pend[(int64_t)x * p + w] = 0;
-    } else {
-      mv = M[(int64_t)x * p + w];
-    }
-    if (__builtin_isnan(mv)) {
-      incomplete = 1;
-    } else {
-      const double neg = mv < 0.0 ? mv : 0.0;
-      s += neg * neg;
-    }
-  }
-  s = block_sum256(s, sh);
-  incomplete = block_or256(incomplete, shi);
-  if (threadIdx.x == 0) {
-    S[x] = s;
-    complete[x] = incomplete ? 0 : 1;
-  }
-  }
-}
-
 // Iteration-level decision after a band, on one wave (ballots and shuffles):
 // the termination test, the threshold update of a round that ended without
 // a root, the root, the next band's threshold state and the compacted alive
-// list.  Its own launch orders it after every row of the score kernel.
-__global__ __launch_bounds__(64) void k_decide(const double* __restrict__ S, uint8_t* __restrict__ alive,
-                                               const uint8_t* __restrict__ complete,
-                                               int32_t* __restrict__ alive_list, int r, int round_end, int t,
-                                               double gamma_mult, const int32_t* __restrict__ forced,
-                                               int forced_len, const int32_t* __restrict__ idx, Ctl* ctl) {
-  if (halted(ctl) || ctl->done) return;
-  const int lane = threadIdx.x;
+// list.
+__device__ void decide_wave(const double* __restrict__ S, uint8_t* __restrict__ alive,
+                            const uint8_t* __restrict__ complete, int32_t* __restrict__ alive_list, int r,
+                            int round_end, int t, double gamma_mult, const int32_t* __restrict__ forced,
+                            int forced_len, const int32_t* __restrict__ idx, Ctl* ctl) {
+  const int lane = threadIdx.x & 63;
   double gamma = ctl->gamma;
   int done = 0;
   for (int guard = 0; guard < 4096; ++guard) {
@@ -811,15 +820,117 @@ __global__ __launch_bounds__(64) void k_decide(const double* __restrict__ S, uin
   }
 }
 
+// Rows whose tests can have changed in a band: the variables of the target
+// blocks, then the alive variables outside them.  One work-group per row
+// forms the pending tests from the chunk partial sums and recomputes the
+// row's score in a fixed order; the last group to finish then decides for
+// the iteration.
+// In the mixed mode it also forms the rounding bound eps of every new test
+// (the sum of the bounds of its four entropies) and the bound of the row's
+// score: a test moved by at most eps changes min(0, M)^2 by at most
+// 2 |min(0, M)| eps + 3 eps^2, and not at all when M >= eps.
+__global__ __launch_bounds__(256) void k_score(double* __restrict__ M, uint8_t* __restrict__ pend,
+                                               const double* __restrict__ P, const double* __restrict__ H,
+                                               double* __restrict__ S, uint8_t* __restrict__ complete,
+                                               const int32_t* alive_list, int r, int p,
+                                               int nchunk, double n, int tb0, int ntb, int mixed,
+                                               double* __restrict__ Meps, const double* __restrict__ eH,
+                                               double* __restrict__ eT, uint8_t* __restrict__ alive,
+                                               int32_t* alive_list_w, int round_end, int t,
+                                               double gamma_mult, const int32_t* __restrict__ forced,
+                                               int forced_len, const int32_t* __restrict__ idx, Ctl* ctl) {
+  __shared__ int s_stop, s_m, s_last, s_wrote;
+  __shared__ double sh[4];
+  __shared__ int shi[4];
+  if (threadIdx.x == 0) {
+    s_stop = halted(ctl) || ctl->done;
+    s_m = ctl->n_alive;
+    s_wrote = 0;
+  }
+  __syncthreads();
+  if (s_stop) return;
+  const int m = s_m;
+  const int t_lo = tb0 * TB, t_hi = min(r, (tb0 + ntb) * TB);
+  const int rows = (t_hi - t_lo) + m;
+  for (int qrow = blockIdx.x; qrow < rows; qrow += gridDim.x) {
+  int x = -1;
+  if (qrow < t_hi - t_lo) {
+    x = t_lo + qrow;
+  } else {
+    const int y = alive_list[qrow - (t_hi - t_lo)];
+    if (y < t_lo || y >= t_hi) x = y;
+  }
+  if (x < 0) continue;  // uniform over the work-group
+  double s = 0.0, es = 0.0;
+  int incomplete = 0;
+  const double hx = H[x];
+  for (int w = threadIdx.x; w < r; w += 256) {
+    if (w == x) continue;
+    double mv, ev = 0.0;
+    if (pend[(int64_t)x * p + w]) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      for (int c = 0; c < nchunk; ++c) {
+        const double* q = P + (((int64_t)c * p + x) * p + w) * 4;
+        a0 += q[0]; a1 += q[1]; a2 += q[2]; a3 += q[3];
+      }
+      const double h_rx = happ_from_sums(a0, a1, n);  // H(r_x^(w))
+      const double h_rw = happ_from_sums(a2, a3, n);  // H(r_w^(x))
+      mv = (H[w] + h_rx) - (hx + h_rw);               // Eq. (Itest)
+      M[(int64_t)x * p + w] = mv;
+      pend[(int64_t)x * p + w] = 0;
+      if (mixed) {
+        ev = (eH[x] + eH[w]) + (happ_err_mixed(a0, a1, n) + happ_err_mixed(a2, a3, n));
+        Meps[(int64_t)x * p + w] = ev;
+      }
+    } else {
+      mv = M[(int64_t)x * p + w];
+      if (mixed && !__builtin_isnan(mv)) ev = Meps[(int64_t)x * p + w];
+    }
+    if (__builtin_isnan(mv)) {
+      incomplete = 1;
+    } else {
+      const double neg = mv < 0.0 ? mv : 0.0;
+      s += neg * neg;
+      if (mv < ev) es += 2.0 * (-neg) * ev + 3.0 * ev * ev;
+    }
+  }
+  s = block_sum256(s, sh);
+  if (mixed) es = block_sum256(es, sh);
+  incomplete = block_or256(incomplete, shi);
+  if (threadIdx.x == 0) {
+    S[x] = s;
+    eT[x] = es;
+    complete[x] = incomplete ? 0 : 1;
+    s_wrote = 1;
+  }
+  }
+  // The last work-group to finish takes the iteration-level decision.  Each
+  // group publishes its scores (release) before it counts itself in; the
+  // last one acquires them.  Nothing waits, so no group can be held up.
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_wrote) __threadfence();
+    const unsigned prev = atomicAdd(&ctl->arrivals, 1u);
+    s_last = prev == gridDim.x - 1 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (threadIdx.x < 64) {
+    decide_wave(S, alive, complete, alive_list_w, r, round_end, t, gamma_mult, forced, forced_len, idx, ctl);
+    if (threadIdx.x == 0) ctl->arrivals = 0;  // ready for the next launch
+  }
+}
+
 hipError_t launch_score(const Dev& d, int buf, const BandArgs& a, int round_end, int t,
-                        double gamma_mult, hipStream_t s) {
-  const int rows = std::min(a.r, a.ntb * TB) + a.r;  // rows when every variable is alive
-  hipLaunchKernelGGL(k_score, dim3(std::min(rows, 512)), dim3(256), 0, s, d.M, d.pend, d.P, d.H, d.S,
-                     d.complete, d.alive_list, a.r, d.p, a.nchunk, (double)d.n, a.tb0, a.ntb, d.ctl);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, s, d.S, d.alive, d.complete, d.alive_list, a.r,
-                     round_end, t, gamma_mult, d.forced, d.forced_len, d.idx[buf], d.ctl);
+                        double gamma_mult, int dense, hipStream_t s) {
+  // rows when every variable is alive; after the first band of an iteration
+  // few are, and a smaller grid keeps idle groups from filling the launch
+  const int rows = std::min(a.r, a.ntb * TB) + a.r;
+  hipLaunchKernelGGL(k_score, dim3(std::min(rows, dense ? 512 : 128)), dim3(256), 0, s, d.M, d.pend, d.P, d.H, d.S,
+                     d.complete, d.alive_list, a.r, d.p, a.nchunk, (double)d.n, a.tb0, a.ntb, d.mixed,
+                     d.Meps, d.eH, d.eT, d.alive, d.alive_list, round_end, t, gamma_mult, d.forced,
+                     d.forced_len, d.idx[buf], d.ctl);
   return hipGetLastError();
 }
 
@@ -829,9 +940,10 @@ hipError_t launch_score(const Dev& d, int buf, const BandArgs& a, int round_end,
 __global__ __launch_bounds__(256) void k_finish_iter(const int32_t* __restrict__ idx,
                                                      const double* __restrict__ S,
                                                      const uint8_t* __restrict__ complete,
-                                                     const double* __restrict__ H, int r, int p, int t,
+                                                     const double* __restrict__ H,
+                                                     const double* __restrict__ eT, int r, int p, int t,
                                                      int32_t* order, double* Tall, uint8_t* Tstate,
-                                                     double* Hall, Ctl* ctl) {
+                                                     double* Hall, double* Terr, Ctl* ctl) {
   if (halted(ctl)) return;
   if (!ctl->done) {
     __syncthreads();
@@ -846,6 +958,7 @@ __global__ __launch_bounds__(256) void k_finish_iter(const int32_t* __restrict__
     Tall[o] = -S[y];
     Tstate[o] = complete[y] ? 1 : 2;
     Hall[o] = H[y];
+    Terr[o] = eT[y];
   }
   if (threadIdx.x == 0) {
     order[t] = idx[ctl->root];
@@ -854,8 +967,8 @@ __global__ __launch_bounds__(256) void k_finish_iter(const int32_t* __restrict__
 }
 
 hipError_t launch_finish_iter(const Dev& d, int buf, int r, int t, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish_iter, dim3(1), dim3(256), 0, s, d.idx[buf], d.S, d.complete, d.H, r,
-                     d.p, t, d.order, d.Tall, d.Tstate, d.Hall, d.ctl);
+  hipLaunchKernelGGL(k_finish_iter, dim3(1), dim3(256), 0, s, d.idx[buf], d.S, d.complete, d.H, d.eT, r,
+                     d.p, t, d.order, d.Tall, d.Tstate, d.Hall, d.Terr, d.ctl);
   return hipGetLastError();
 }
 
@@ -949,15 +1062,17 @@ hipError_t launch_update(const Dev& d, int buf, int r, int refresh, hipStream_t 
 
 // Last remaining variable: appended without a comparison (Alg. 2).
 __global__ void k_last(const int32_t* idx, int p, int t, int32_t* order, double* Tall, uint8_t* Tstate,
-                       const Ctl* ctl) {
+                       double* Terr, const Ctl* ctl) {
   if (halted(ctl)) return;
   order[t] = idx[0];
   Tall[(int64_t)t * p + idx[0]] = 0.0;
   Tstate[(int64_t)t * p + idx[0]] = 1;
+  Terr[(int64_t)t * p + idx[0]] = 0.0;
 }
 
 hipError_t launch_last(const Dev& d, int buf, int t, hipStream_t s) {
-  hipLaunchKernelGGL(k_last, dim3(1), dim3(1), 0, s, d.idx[buf], d.p, t, d.order, d.Tall, d.Tstate, d.ctl);
+  hipLaunchKernelGGL(k_last, dim3(1), dim3(1), 0, s, d.idx[buf], d.p, t, d.order, d.Tall, d.Tstate, d.Terr,
+                     d.ctl);
   return hipGetLastError();
 }
 

@@ -36,7 +36,7 @@ struct Ctl {
   int32_t status;       // Status of the first error
   int32_t bad_i, bad_j; // compacted positions (pair error) or original index (row error)
   int32_t round;        // threshold round of the current iteration
-  uint32_t pad0;
+  uint32_t arrivals;     // work-groups of the running score launch that have finished
   int32_t n_alive;        // entries of the alive list (variables with S <= gamma)
   double last_root_S;     // score of the previous iteration's root (adaptive gamma0)
   unsigned long long pairs_evaluated;
@@ -58,7 +58,12 @@ struct Dev {
   double* Sig[2] = {nullptr, nullptr};
   double* dsc[2] = {nullptr, nullptr};
   int32_t* idx[2] = {nullptr, nullptr};   // [p] compacted position -> original index
+  int mixed = 0;             // 1 = mixed-precision per-sample terms
   double* H = nullptr;       // [p] entropy estimate per compacted row
+  double* eH = nullptr;      // [p] rounding bound of H (mixed mode; 0 in FP64 mode)
+  double* Meps = nullptr;    // p x p rounding bound of each evaluated test (mixed mode)
+  double* eT = nullptr;      // [p] rounding bound of each score (mixed mode)
+  double* Terr = nullptr;    // [p*p] eT per iteration, by original index
   double* M = nullptr;       // p x p test matrix of the iteration (NaN = not evaluated)
   double* S = nullptr;       // [p] scores (sum of min(0, M)^2 over evaluated pairs)
   uint8_t* alive = nullptr;  // [p] S <= gamma at the last snapshot
@@ -100,7 +105,7 @@ hipError_t launch_entropy(const Dev& d, int buf, int r, int mixed, hipStream_t s
 hipError_t launch_iter_init(const Dev& d, int r, double gamma0, double adapt, hipStream_t s);
 hipError_t launch_pair_band(const Dev& d, int buf, const BandArgs& a, int mixed, int dense, hipStream_t s);
 hipError_t launch_score(const Dev& d, int buf, const BandArgs& a, int round_end, int t,
-                        double gamma_mult, hipStream_t s);
+                        double gamma_mult, int dense, hipStream_t s);
 hipError_t launch_finish_iter(const Dev& d, int buf, int r, int t, hipStream_t s);
 hipError_t launch_record_M(const Dev& d, int buf, int r, int t, hipStream_t s);
 hipError_t launch_update(const Dev& d, int buf, int r, int refresh, hipStream_t s);

@@ -107,6 +107,8 @@ def test_threshold_keeps_order_and_complete_scores():
     for seed, (p, n) in enumerate([(10, 1000), (27, 3001), (60, 4000)]):
         ds = synth.lingam_dataset(p, n, 0.3, "mixed", rng=np.random.default_rng(50 + seed))
         off = lg.fit_order(ds.X, use_threshold=False)
+        # every unordered pair of every iteration, counted once (device-wide counters)
+        assert off.pairs_evaluated == (p + 1) * p * (p - 1) // 6
         for g0, c, bt in ((1e-6, 4.0, 1), (1e-9, 2.0, 1), (1e-3, 10.0, 1), (0.0, 4.0, 1),
                           (0.0, 1.5, 2), (1e-6, 4.0, 0)):
             on = lg.fit_order(ds.X, use_threshold=True, gamma0=g0, gamma_mult=c, band_blocks=bt)
@@ -128,6 +130,7 @@ def test_config2_fp64_parity():
     o = oracle.fit_order(ds.X, M_iters=100)
     g = lg.fit_order(ds.X, precision="fp64", use_threshold=False, record_M_iters=100)
     assert list(g.order) == list(o["order"])
+    assert g.pairs_evaluated == 101 * 100 * 99 // 6
     check_fp64(g, o, 100)
     on = lg.fit_order(ds.X, precision="fp64")   # default: threshold on
     assert list(on.order) == list(o["order"])
@@ -207,6 +210,67 @@ def test_mixed_teacher_forced_scores():
     dH = np.nanmax(np.abs(g.H - o["H"]))
     _log("mixed cfg2: max|dM| %.3e  max|dT| %.3e  max|dH| %.3e" % (dM, dT.max(), dH))
     assert dM < 1e-5 and dH < 1e-6
+    # the a-priori rounding bound of every score holds against the FP64 oracle
+    # (plus the FP64 pipeline tolerance of the end-to-end comparison)
+    tol64 = 1e-9 * np.abs(o["T"][fin]) + 1e-12
+    ratio = dT / (g.T_err[fin] + tol64)
+    _log("mixed cfg2: max |dT| / (bound + tol) = %.3e, max bound %.3e" % (ratio.max(), g.T_err[fin].max()))
+    assert np.all(g.T_err[fin] >= 0.0) and ratio.max() <= 1.0
+    # gap rule: where the bound separates the top score from every other, the
+    # mixed argmax is the oracle's root
+    certified = 0
+    for t in range(ds.X.shape[0] - 1):
+        row, err = g.T[t], g.T_err[t]
+        live = np.isfinite(row)
+        top = int(np.flatnonzero(live)[np.argmax(row[live])])
+        others = live.copy()
+        others[top] = False
+        if row[top] - err[top] > np.max(row[others] + err[others]):
+            certified += 1
+            assert top == o["order"][t], "iteration %d certified but argmax differs" % t
+    _log("mixed cfg2: %d of %d iterations certified by the gap rule" % (certified, ds.X.shape[0] - 1))
+
+
+def _gap_certified(T, E, state, t):
+    """Root position of iteration t of a mixed run and whether the rounding
+    bounds separate it from every other variable (a pruned variable's partial
+    T is an upper bound of its full score, so it competes with that value)."""
+    row, err = T[t], E[t]
+    live = np.isfinite(row)
+    comp = live & (state[t] == 1)
+    top = int(np.flatnonzero(comp)[np.argmax(row[comp])])
+    others = live.copy()
+    others[top] = False
+    if not others.any():
+        return top, True
+    return top, bool(row[top] - err[top] > np.max(row[others] + err[others]))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("chunk", [0, 1024])
+def test_mixed_free_running_order_gap_rule(cfg3, chunk):
+    """Free-running mixed order against the FP64 order at full size: the first
+    iteration where they differ must be one the rounding bound cannot certify."""
+    X = cfg3.X
+    g64 = lg.fit_order(X, precision="fp64")
+    gm = lg.fit_order(X, precision="mixed", chunk_samples=chunk)
+    p = X.shape[0]
+    diff = np.flatnonzero(gm.order != g64.order)
+    first = int(diff[0]) if diff.size else p
+    cert = 0
+    for t in range(min(first + 1, p - 1)):
+        top, ok = _gap_certified(gm.T, gm.T_err, gm.T_state, t)
+        assert top == gm.order[t]
+        cert += ok
+        if t == first:
+            assert not ok, "iteration %d: mixed root %d certified but FP64 root is %d" % (
+                t, gm.order[t], g64.order[t])
+    both = (gm.T_state[:first] == 1) & (g64.T_state[:first] == 1)
+    dT = np.abs(gm.T[:first][both] - g64.T[:first][both])
+    bound = gm.T_err[:first][both] + 1e-9 * np.abs(g64.T[:first][both]) + 1e-12
+    _log("mixed chunk=%d: orders agree on %d of %d iterations; %d certified; max|dT| %.3e; "
+         "max |dT|/bound %.3e" % (chunk, first, p, cert, dT.max(), (dT / bound).max()))
+    assert np.all(dT <= bound)
 
 
 # ---- edge cases and input forms ------------------------------------------------
