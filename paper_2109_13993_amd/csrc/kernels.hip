@@ -684,12 +684,11 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(
 
 // Work-group shapes of the pair kernel (results do not depend on them).
 // Dense bands (every variable still alive): 16 rows x 8 targets per wave,
-// so each staged target block is shared by 16 rows.  Sparse bands: 4 rows,
-// each row's 8 targets split over 4 waves of 2, giving the few alive rows
-// four times as many (and shorter) waves, and 512-sample LDS stages so a
-// chunk needs only four load round trips.  The FP64 variant uses fewer
-// waves per group because its terms need more registers per lane.
-// Work-groups of one shape that the device holds at once (all CUs).
+// so each staged target block is shared by 16 rows.  Sparse bands: one row
+// per group, its 8 targets split over 4 waves of 2, so the few alive rows
+// spread over many small groups that the CUs hold four at a time.  The FP64
+// variant uses fewer waves per group because its terms need more registers
+// per lane.
 template <bool MIXED, int RG, int TPW, int PS>
 static int resident_groups() {
   static std::atomic<int> cached{0};
@@ -726,7 +725,7 @@ hipError_t launch_pair_band(const Dev& d, int buf, const BandArgs& a, int mixed,
   if (mixed && dense)
     launch_pair_shape<true, 16, 8, 256>(d, buf, a, s, 1 << 16);
   else if (mixed)
-    launch_pair_shape<true, 4, 2, 512>(d, buf, a, s, 1);
+    launch_pair_shape<true, 1, 2, 256>(d, buf, a, s, 1);
   else if (dense)
     launch_pair_shape<false, 4, 8, 256>(d, buf, a, s, 1 << 16);
   else
@@ -737,72 +736,83 @@ hipError_t launch_pair_band(const Dev& d, int buf, const BandArgs& a, int mixed,
 // ============================================================================
 // a5/a6: tests, scores, threshold state, termination and root
 // ============================================================================
-// Iteration-level decision after a band, on one wave (ballots and shuffles):
-// the termination test, the threshold update of a round that ended without
-// a root, the root, the next band's threshold state and the compacted alive
-// list.
-__device__ void decide_wave(const double* __restrict__ S, uint8_t* __restrict__ alive,
-                            const uint8_t* __restrict__ complete, int32_t* __restrict__ alive_list, int r,
-                            int round_end, int t, double gamma_mult, const int32_t* __restrict__ forced,
-                            int forced_len, const int32_t* __restrict__ idx, Ctl* ctl) {
-  const int lane = threadIdx.x & 63;
+// Iteration-level decision after a band, taken by one work-group of 256
+// threads: the termination test, the threshold update of a round that ended
+// without a root, the root, the next band's threshold state and the
+// compacted alive list.  One pass over the scores gives the smallest
+// complete score (with its lowest position) and the smallest incomplete one;
+// for a threshold gamma, some complete score is <= gamma iff the first is,
+// and some incomplete one iff the second is, so the threshold loop needs no
+// further pass.
+__device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__ alive,
+                             const uint8_t* __restrict__ complete, int32_t* __restrict__ alive_list, int r,
+                             int round_end, int t, double gamma_mult, const int32_t* __restrict__ forced,
+                             int forced_len, const int32_t* __restrict__ idx, Ctl* ctl) {
+  __shared__ double sh_c[4], sh_i[4];
+  __shared__ int sh_ci[4], sh_pos[4], sh_cnt[4], sh_has[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int want = t < forced_len ? forced[t] : -1;
+  double minc = INFINITY, mini = INFINITY;
+  int ci = 0x7fffffff, pos = -1, has = 0;  // has: bit 0 some complete row, bit 1 some incomplete row
+  for (int y = tid; y < r; y += 256) {
+    const double sy = S[y];
+    if (complete[y]) {
+      has |= 1;
+      if (sy < minc || (sy == minc && y < ci)) { minc = sy; ci = y; }
+    } else {
+      has |= 2;
+      mini = fmin(mini, sy);
+    }
+    if (want >= 0 && idx[y] == want) pos = y;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double oc = __shfl_xor(minc, off, 64);
+    const int oci = __shfl_xor(ci, off, 64);
+    if (oc < minc || (oc == minc && oci < ci)) { minc = oc; ci = oci; }
+    mini = fmin(mini, __shfl_xor(mini, off, 64));
+    pos = max(pos, __shfl_xor(pos, off, 64));
+    has |= __shfl_xor(has, off, 64);
+  }
+  if (lane == 0) { sh_c[wv] = minc; sh_ci[wv] = ci; sh_i[wv] = mini; sh_pos[wv] = pos; sh_has[wv] = has; }
+  __syncthreads();
+  minc = sh_c[0]; ci = sh_ci[0]; mini = sh_i[0]; pos = sh_pos[0]; has = sh_has[0];
+  for (int w = 1; w < 4; ++w) {
+    if (sh_c[w] < minc || (sh_c[w] == minc && sh_ci[w] < ci)) { minc = sh_c[w]; ci = sh_ci[w]; }
+    mini = fmin(mini, sh_i[w]);
+    pos = max(pos, sh_pos[w]);
+    has |= sh_has[w];
+  }
+  // termination: some complete score <= gamma and every incomplete one > gamma;
+  // a round that ends with every score above gamma raises gamma by c
   double gamma = ctl->gamma;
   int done = 0;
   for (int guard = 0; guard < 4096; ++guard) {
-    // termination: some complete score <= gamma, every incomplete score > gamma
-    int cand = 0, blocked = 0, below = 0;
-    for (int y = lane; y < r; y += 64) {
-      if (S[y] <= gamma) {
-        below = 1;
-        if (complete[y]) cand = 1; else blocked = 1;
-      }
-    }
-    cand = __any(cand);
-    blocked = __any(blocked);
-    below = __any(below);
+    const bool cand = (has & 1) && minc <= gamma;
+    const bool blocked = (has & 2) && mini <= gamma;
     if (cand && !blocked) { done = 1; break; }
-    if (round_end && !below) { gamma = gamma > 0.0 ? gamma * gamma_mult : 1e-300; continue; }
+    if (round_end && !cand && !blocked) { gamma = gamma > 0.0 ? gamma * gamma_mult : 1e-300; continue; }
     break;
   }
-  int root = -1;
-  if (done) {
-    // root = argmin S over complete variables, lowest position on ties
-    double best = INFINITY;
-    int bi = 0x7fffffff;
-    for (int y = lane; y < r; y += 64) {
-      if (!complete[y]) continue;
-      const double sy = S[y];
-      if (sy < best || (sy == best && y < bi)) { best = sy; bi = y; }
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob < best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    root = bi;
-    if (t < forced_len) {
-      // teacher forcing: the root is given; find its position
-      int pos = -1;
-      for (int y = lane; y < r; y += 64)
-        if (idx[y] == forced[t]) pos = y;
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) pos = max(pos, __shfl_xor(pos, off, 64));
-      root = pos;
-    }
-  }
-  // threshold state for the next band, and the compacted alive list
+  const int root = !done ? -1 : (want >= 0 ? pos : (ci == 0x7fffffff ? -1 : ci));
+  // threshold state for the next band and the compacted alive list, in
+  // ascending position
   int base = 0;
-  for (int y0 = 0; y0 < r; y0 += 64) {
-    const int y = y0 + lane;
+  for (int y0 = 0; y0 < r; y0 += 256) {
+    const int y = y0 + tid;
     const int a = y < r && S[y] <= gamma ? 1 : 0;
     if (y < r) alive[y] = (uint8_t)a;
     const unsigned long long bal = __ballot(a);
-    const int before = __popcll(bal & ((1ull << lane) - 1ull));
-    if (a) alive_list[base + before] = y;
-    base += __popcll(bal);
+    if (lane == 0) sh_cnt[wv] = __popcll(bal);
+    __syncthreads();
+    int before = base;
+    for (int w = 0; w < wv; ++w) before += sh_cnt[w];
+    before += __popcll(bal & ((1ull << lane) - 1ull));
+    if (a) alive_list[before] = y;
+    base += (sh_cnt[0] + sh_cnt[1]) + (sh_cnt[2] + sh_cnt[3]);
+    __syncthreads();
   }
-  if (lane == 0) {
+  if (tid == 0) {
     ctl->gamma = gamma;
     ctl->n_alive = base;
     if (done) {
@@ -916,10 +926,8 @@ __global__ __launch_bounds__(256) void k_score(double* __restrict__ M, uint8_t* 
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  if (threadIdx.x < 64) {
-    decide_wave(S, alive, complete, alive_list_w, r, round_end, t, gamma_mult, forced, forced_len, idx, ctl);
-    if (threadIdx.x == 0) ctl->arrivals = 0;  // ready for the next launch
-  }
+  decide_group(S, alive, complete, alive_list_w, r, round_end, t, gamma_mult, forced, forced_len, idx, ctl);
+  if (threadIdx.x == 0) ctl->arrivals = 0;  // ready for the next launch
 }
 
 hipError_t launch_score(const Dev& d, int buf, const BandArgs& a, int round_end, int t,
