@@ -113,8 +113,9 @@ typedef struct lingam_result {
   double seconds_device;      /* device time from the first to the last kernel */
   double seconds_pair_kernel; /* summed duration of the pair-kernel launches (opts.profile) */
   uint64_t pair_kernel_launches;  /* pair-kernel launches (counted when opts.profile) */
-  int32_t iterations;         /* scored iterations run */
+  int32_t iterations;         /* roots placed in order[] */
   int32_t bad_i, bad_j;       /* diagnostics for NONFINITE / DEGENERATE, else -1 */
+  int32_t status;             /* lingam_status of this result (the per-set status of a batch) */
 } lingam_result;
 
 /* Fill *o with the defaults listed above (struct_size set). */
@@ -142,9 +143,19 @@ typedef struct lingam_dataset {
   int64_t n_idx;
 } lingam_dataset;
 
-/* Causal orders of `count` independent data sets in one persistent launch
- * per iteration step.  outs[k] receives the result of sets[k]; the options
- * apply to every set (forced_order and record_M_iters must be unset). */
+/* Causal orders of `count` (<= 65535) independent data sets.  Every kernel
+ * launch covers all sets of the batch at the same iteration (one descriptor
+ * per set on the device), so many small searches share each launch; a set
+ * whose iteration needs more threshold rounds than were queued leaves the
+ * batch and is finished on its own.  The results are those of separate
+ * lingam_fit_order calls with the same options, bit for bit.
+ *   sets[k].X: host or device memory per opts->x_on_device, with opts->x_dtype
+ *     and opts->layout; a bootstrap set (sample_idx != NULL) needs a binary64
+ *     p x n base, its sample_idx is host memory, n_idx samples are drawn.
+ *   outs[k]: as for lingam_fit_order (M unused); outs[k].status is that set's
+ *     status.  forced_order and record_M_iters must be unset (UNSUPPORTED).
+ * Returns LINGAM_OK if every set succeeded, else the status of the first set
+ * that failed (the other results are still filled). */
 lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets,
                                      const lingam_opts* o, lingam_result* outs);
 

@@ -71,6 +71,7 @@ class LingamResult(ctypes.Structure):
         ("iterations", ctypes.c_int32),
         ("bad_i", ctypes.c_int32),
         ("bad_j", ctypes.c_int32),
+        ("status", ctypes.c_int32),
     ]
 
 
@@ -245,6 +246,84 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
                      bands=res.bands, seconds_total=res.seconds_total,
                      seconds_device=res.seconds_device, seconds_pair_kernel=res.seconds_pair_kernel,
                      pair_kernel_launches=res.pair_kernel_launches, iterations=res.iterations)
+
+
+def fit_order_batch(datasets, precision: str = "fp64", use_threshold: bool = True, gamma0: float = 0.0,
+                    gamma_mult: float = 0.0, cov_refresh_every=None, max_roots: int = 0,
+                    band_blocks: int = 0, chunk_samples: int = 0, want_T: bool = True,
+                    want_H: bool = False, profile: bool = False, stream=None):
+    """Causal orders of many data sets in one batched search (lingam_fit_order_batch).
+
+    `datasets` is a list whose items are either a p x n array (numpy, float64
+    or float32; all of one dtype) or a tuple (base, sample_idx): a bootstrap
+    resample of the columns of the float64 p x n array `base` (the same base
+    object may be shared by many items; it is uploaded once).  Returns a list
+    of FitResult; a data set that failed has extra["status"] != 0.
+    """
+    lib = load_library()
+    o, _ = _make_opts(precision, use_threshold, gamma0, gamma_mult, cov_refresh_every, max_roots,
+                      None, 0, band_blocks, chunk_samples, profile=profile)
+    if stream is not None:
+        o.stream = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    count = len(datasets)
+    sets = (LingamDataset * count)()
+    outs = (LingamResult * count)()
+    keep, results = [], []
+    dtype = None
+    for k, item in enumerate(datasets):
+        if isinstance(item, tuple):
+            base, idx = item
+            base = np.ascontiguousarray(base, dtype=np.float64)
+            idx = np.ascontiguousarray(idx, dtype=np.int64)
+            keep += [base, idx]
+            sets[k].X = ctypes.c_void_p(base.ctypes.data)
+            sets[k].p, sets[k].n = base.shape
+            sets[k].sample_idx = idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            sets[k].n_idx = idx.size
+            p = base.shape[0]
+        else:
+            arr = np.asarray(item)
+            if arr.dtype not in (np.float64, np.float32):
+                arr = arr.astype(np.float64)
+            arr = np.ascontiguousarray(arr)
+            if dtype is None:
+                dtype = arr.dtype
+            elif arr.dtype != dtype:
+                raise TypeError("all data sets of a batch must have one dtype")
+            keep.append(arr)
+            sets[k].X = ctypes.c_void_p(arr.ctypes.data)
+            sets[k].p, sets[k].n = arr.shape
+            p = arr.shape[0]
+        r = dict(order=np.full(p, -1, dtype=np.int32),
+                 T=np.full((p, p), np.nan) if want_T else None,
+                 T_state=np.zeros((p, p), dtype=np.uint8) if want_T else None,
+                 H=np.full((p, p), np.nan) if want_H else None,
+                 T_err=np.full((p, p), np.nan) if want_T else None)
+        outs[k].order = r["order"].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        if want_T:
+            outs[k].T = r["T"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            outs[k].T_state = r["T_state"].ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+            outs[k].T_err_bound = r["T_err"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if want_H:
+            outs[k].H = r["H"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        results.append(r)
+    o.x_dtype = 1 if dtype == np.float32 else 0
+    st = lib.lingam_fit_order_batch(count, sets, ctypes.byref(o), outs)
+    if st != OK and all(outs[k].status == OK for k in range(count)):
+        raise LingamError(st, lib.lingam_last_error().decode())
+    del keep
+    res = []
+    for k, r in enumerate(results):
+        out = outs[k]
+        res.append(FitResult(order=r["order"], T=r["T"], T_state=r["T_state"], H=r["H"], T_err=r["T_err"],
+                             pairs_evaluated=out.pairs_evaluated, pair_samples=out.pair_samples,
+                             pairs_computed=out.pairs_computed, threshold_rounds=out.threshold_rounds,
+                             bands=out.bands, seconds_total=out.seconds_total,
+                             seconds_device=out.seconds_device,
+                             seconds_pair_kernel=out.seconds_pair_kernel,
+                             pair_kernel_launches=out.pair_kernel_launches, iterations=out.iterations,
+                             extra={"status": out.status, "bad_i": out.bad_i, "bad_j": out.bad_j}))
+    return res
 
 
 def status_string(status: int) -> str:

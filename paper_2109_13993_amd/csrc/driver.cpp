@@ -9,6 +9,12 @@
 // host only queues launches; it synchronises once every SYNC_EVERY
 // iterations to check for errors and for iterations that needed more
 // threshold rounds than were queued.
+//
+// lingam_fit_order_batch runs many independent searches through the same
+// kernels: every launch covers all data sets of the batch (one descriptor
+// each, grid dimension z), each at the same iteration.  A data set whose
+// iteration needs more threshold rounds than were queued sits out the rest
+// of the batch and is finished on its own afterwards.
 #include "lingam.h"
 #include "lingam_internal.h"
 
@@ -87,48 +93,60 @@ Plan make_plan(int64_t n, const lingam_opts& o) {
   return pl;
 }
 
-// Round-0 bands of an iteration with r variables: consecutive groups of
-// `band_blocks` target blocks.  Later rounds use one band with every block.
+// Round-0 bands of an iteration at which the largest data set has r
+// variables: consecutive groups of `band_blocks` target blocks (clipped on
+// the device to the blocks each data set has).  Later rounds use one band
+// with every block.
 std::vector<BandArgs> round0_bands(int r, const Plan& pl, bool threshold) {
   std::vector<BandArgs> out;
   const int nb = (r + TB - 1) / TB;
   const int K = threshold ? std::max(1, pl.band_blocks) : nb;
-  for (int tb0 = 0; tb0 < nb; tb0 += K)
-    out.push_back(BandArgs{r, nb, tb0, std::min(K, nb - tb0), pl.nchunk, pl.chunk, 0});
+  for (int tb0 = 0; tb0 < nb; tb0 += K) out.push_back(BandArgs{tb0, K, pl.chunk});
   return out;
 }
 
-BandArgs full_band(int r, const Plan& pl) {
-  const int nb = (r + TB - 1) / TB;
-  return BandArgs{r, nb, 0, nb, pl.nchunk, pl.chunk, 0};
-}
+BandArgs full_band(const Plan& pl) { return BandArgs{0, 1 << 30, pl.chunk}; }
 
 lingam_status fail(lingam_status st, const std::string& msg) {
   g_last_error = msg;
   return st;
 }
 
-lingam_status validate(const void* X, int64_t n, int64_t p, const lingam_opts& o, const lingam_result* out) {
-  if (!X) return fail(LINGAM_E_INVALID, "X is NULL");
-  if (!out || !out->order) return fail(LINGAM_E_INVALID, "result or result->order is NULL");
+lingam_status validate_opts(const lingam_opts& o) {
   if (o.struct_size != sizeof(lingam_opts)) return fail(LINGAM_E_INVALID, "opts.struct_size mismatch");
-  if (n < 2) return fail(LINGAM_E_INVALID, "n must be >= 2");
-  if (p < 1) return fail(LINGAM_E_INVALID, "p must be >= 1");
-  if (p > 65535) return fail(LINGAM_E_INVALID, "p must be <= 65535");
-  if (n > ((int64_t)1 << 40) || p * n > ((int64_t)1 << 40)) return fail(LINGAM_E_INVALID, "p * n too large");
   if (o.precision != LINGAM_PREC_FP64 && o.precision != LINGAM_PREC_MIXED)
     return fail(LINGAM_E_INVALID, "unknown precision");
   if (o.layout != LINGAM_LAYOUT_VAR_MAJOR && o.layout != LINGAM_LAYOUT_SAMPLE_MAJOR)
     return fail(LINGAM_E_INVALID, "unknown layout");
   if (o.x_dtype != 0 && o.x_dtype != 1) return fail(LINGAM_E_INVALID, "x_dtype must be 0 or 1");
   if (o.max_roots < 0) return fail(LINGAM_E_INVALID, "max_roots < 0");
-  if (o.record_M_iters < 0 || o.record_M_iters > p) return fail(LINGAM_E_INVALID, "record_M_iters out of range");
-  if (o.record_M_iters > 0 && !out->M) return fail(LINGAM_E_INVALID, "record_M_iters > 0 but result->M is NULL");
   if (o.chunk_samples < 0 || o.chunk_samples % SUB != 0)
     return fail(LINGAM_E_INVALID, "chunk_samples must be a multiple of 256");
   if (o.band_blocks < 0) return fail(LINGAM_E_INVALID, "band_blocks < 0");
-  if (o.forced_len < 0 || o.forced_len > p || (o.forced_len > 0 && !o.forced_order))
+  if (o.record_M_iters < 0) return fail(LINGAM_E_INVALID, "record_M_iters < 0");
+  if (o.forced_len < 0 || (o.forced_len > 0 && !o.forced_order))
     return fail(LINGAM_E_INVALID, "bad forced_order / forced_len");
+  return LINGAM_OK;
+}
+
+lingam_status validate_shape(int64_t n, int64_t p) {
+  if (n < 2) return fail(LINGAM_E_INVALID, "n must be >= 2");
+  if (p < 1) return fail(LINGAM_E_INVALID, "p must be >= 1");
+  if (p > 65535) return fail(LINGAM_E_INVALID, "p must be <= 65535");
+  if (n > ((int64_t)1 << 40) || p * n > ((int64_t)1 << 40)) return fail(LINGAM_E_INVALID, "p * n too large");
+  return LINGAM_OK;
+}
+
+lingam_status validate(const void* X, int64_t n, int64_t p, const lingam_opts& o, const lingam_result* out) {
+  if (!X) return fail(LINGAM_E_INVALID, "X is NULL");
+  if (!out || !out->order) return fail(LINGAM_E_INVALID, "result or result->order is NULL");
+  lingam_status st = validate_opts(o);
+  if (st != LINGAM_OK) return st;
+  st = validate_shape(n, p);
+  if (st != LINGAM_OK) return st;
+  if (o.record_M_iters > p) return fail(LINGAM_E_INVALID, "record_M_iters out of range");
+  if (o.record_M_iters > 0 && !out->M) return fail(LINGAM_E_INVALID, "record_M_iters > 0 but result->M is NULL");
+  if (o.forced_len > p) return fail(LINGAM_E_INVALID, "bad forced_order / forced_len");
   if (o.forced_len > 0) {
     std::vector<char> seen((size_t)p, 0);
     for (int k = 0; k < o.forced_len; ++k) {
@@ -153,6 +171,7 @@ void reset_result(lingam_result* out, int64_t p, int rec) {
   out->pair_kernel_launches = 0;
   out->iterations = 0;
   out->bad_i = out->bad_j = -1;
+  out->status = LINGAM_OK;
 }
 
 // Optional timing of the pair-kernel launches: an event pair around each
@@ -183,65 +202,226 @@ struct PairTimer {
   }
 };
 
+// Buffers of one data set (device memory from `al`), its iteration limit
+// and host-side shape.
+struct SetInfo {
+  int64_t p = 0, n = 0;
+  int limit = 0;        // iterations to run (p, or max_roots)
+  Ctl* ctl = nullptr;   // its control block inside the call's Ctl array
+};
+
+Dev alloc_set(Allocs& al, int64_t n, int64_t p, const Plan& pl, const lingam_opts& o, bool mixed, Ctl* ctl) {
+  Dev d;
+  d.p = (int)p;
+  d.n = n;
+  d.ldz = round_up(n, SUB);
+  d.nchunk = (int)((n + pl.chunk - 1) / pl.chunk);
+  d.mixed = mixed ? 1 : 0;
+  d.x_dtype = o.x_dtype;
+  d.layout = o.layout;
+  const size_t P = (size_t)p, pp = P * P;
+  d.Z[0] = al.get<double>(P * d.ldz);
+  d.Z[1] = al.get<double>(P * d.ldz);
+  d.Sig[0] = al.get<double>(pp);
+  d.Sig[1] = al.get<double>(pp);
+  d.dsc[0] = al.get<double>(P);
+  d.dsc[1] = al.get<double>(P);
+  d.idx[0] = al.get<int32_t>(P);
+  d.idx[1] = al.get<int32_t>(P);
+  d.H = al.get<double>(P);
+  d.eH = al.get<double>(P);
+  d.eT = al.get<double>(P);
+  d.Meps = al.get<double>(pp);
+  d.Terr = al.get<double>(pp);
+  d.M = al.get<double>(pp);
+  d.S = al.get<double>(P);
+  d.alive = al.get<uint8_t>(P);
+  d.alive_list = al.get<int32_t>(P);
+  d.complete = al.get<uint8_t>(P);
+  d.pend = al.get<uint8_t>(pp);
+  d.P = al.get<double>((size_t)d.nchunk * pp * 4);
+  d.ctl = ctl;
+  d.order = al.get<int32_t>(P);
+  d.Tall = al.get<double>(pp);
+  d.Tstate = al.get<uint8_t>(pp);
+  d.Hall = al.get<double>(pp);
+  d.rec = o.record_M_iters;
+  d.Mrec = d.rec > 0 ? al.get<double>((size_t)d.rec * pp) : nullptr;
+  d.stats = al.get<double>(2 * P);
+  d.gram_slices_max = GRAM_SLICES_MAX;
+  d.Gp = al.get<double>((size_t)GRAM_SLICES_MAX * pp);
+  d.forced_len = o.forced_len;
+  int32_t* forced_dev = al.get<int32_t>(std::max<size_t>(1, (size_t)o.forced_len));
+  d.forced = forced_dev;
+  return d;
+}
+
+// Initial contents of one data set's buffers (queued on s; fills by kernel,
+// no memset nodes).
+void init_set(const Dev& d, const lingam_opts& o, int limit, hipStream_t s, std::vector<int32_t>& iota) {
+  const size_t P = (size_t)d.p, pp = P * P;
+  if (o.forced_len > 0)
+    HIPCHK(hipMemcpyAsync(const_cast<int32_t*>(d.forced), o.forced_order, sizeof(int32_t) * o.forced_len,
+                          hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d.idx[0], iota.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_fill(d.Z[1], (int64_t)(P * d.ldz), 0.0, s));
+  HIPCHK(launch_fill(d.M, (int64_t)pp, NAN, s));
+  HIPCHK(launch_fill_u8(d.pend, (int64_t)pp, 0, s));
+  HIPCHK(launch_fill(d.Tall, (int64_t)pp, NAN, s));
+  HIPCHK(launch_fill_u8(d.Tstate, (int64_t)pp, 0, s));
+  HIPCHK(launch_fill(d.Hall, (int64_t)pp, NAN, s));
+  HIPCHK(launch_fill(d.Terr, (int64_t)pp, NAN, s));
+  if (d.Mrec) HIPCHK(launch_fill(d.Mrec, (int64_t)d.rec * (int64_t)pp, NAN, s));
+  HIPCHK(launch_fill_u8(reinterpret_cast<uint8_t*>(d.order), (int64_t)(4 * P), 0xff, s));
+  (void)limit;
+}
+
+// Launch sequence of a batch (a single search is a batch of one).
 struct Fit {
   PairTimer* timer = nullptr;
-  void pair(int buf, const BandArgs& a, bool dense = false) {
-    if (timer && timer->on) {
-      HIPCHK(hipEventRecord(timer->next(), s));
-      HIPCHK(launch_pair_band(d, buf, a, mixed, dense ? 1 : 0, s));
-      HIPCHK(hipEventRecord(timer->next(), s));
-      ++timer->launches;
-    } else {
-      HIPCHK(launch_pair_band(d, buf, a, mixed, dense ? 1 : 0, s));
-    }
-  }
-  Dev d;
+  Batch b;
   Plan pl;
   lingam_opts o;
   hipStream_t s;
-  int p;
-  int64_t n;
-  bool mixed;
   bool threshold;
   double gamma0, gmult;
+  int rec = 0;
+  std::vector<int64_t> ps;   // p of every data set
+  std::vector<int> limits;   // iterations of every data set
 
-  void queue_rounds(int t, int r, int buf, int nrounds) {
+  void pair(int t, const BandArgs& a, bool dense = false) {
+    if (timer && timer->on) {
+      HIPCHK(hipEventRecord(timer->next(), s));
+      HIPCHK(launch_pair_band(b, t, a, dense ? 1 : 0, s));
+      HIPCHK(hipEventRecord(timer->next(), s));
+      ++timer->launches;
+    } else {
+      HIPCHK(launch_pair_band(b, t, a, dense ? 1 : 0, s));
+    }
+  }
+
+  void queue_rounds(int t, int nrounds) {
+    const int r = b.p_max - t;
     for (int rd = 0; rd < nrounds; ++rd) {
       if (rd == 0) {
         auto bands = round0_bands(r, pl, threshold);
-        for (size_t b = 0; b < bands.size(); ++b) {
-          pair(buf, bands[b], b == 0);  // the first band still has every variable alive
-          HIPCHK(launch_score(d, buf, bands[b], b + 1 == bands.size() ? 1 : 0, t, gmult, b == 0 ? 1 : 0, s));
+        for (size_t k = 0; k < bands.size(); ++k) {
+          pair(t, bands[k], k == 0);  // the first band still has every variable alive
+          HIPCHK(launch_score(b, t, bands[k], gmult, k == 0 ? 1 : 0, s));
         }
       } else {
-        pair(buf, full_band(r, pl));
-        HIPCHK(launch_score(d, buf, full_band(r, pl), 1, t, gmult, 0, s));
+        pair(t, full_band(pl));
+        HIPCHK(launch_score(b, t, full_band(pl), gmult, 0, s));
       }
     }
   }
 
-  void queue_tail(int t, int r, int buf) {
-    HIPCHK(launch_finish_iter(d, buf, r, t, s));
-    if (t < d.rec) HIPCHK(launch_record_M(d, buf, r, t, s));
+  void queue_tail(int t) {
+    HIPCHK(launch_finish_iter(b, t, s));
+    if (t < rec) HIPCHK(launch_record_M(b, t, s));
     const bool refresh = o.cov_refresh_every > 0 && ((t + 1) % o.cov_refresh_every == 0);
-    HIPCHK(launch_update(d, buf, r, refresh ? 1 : 0, s));
+    HIPCHK(launch_update(b, t, refresh ? 1 : 0, s));
   }
 
+  // iteration t of every data set that has one (p - t >= 2 and t < its limit);
+  // a data set with one variable left appends it
   void queue_iteration(int t) {
-    const int r = p - t, buf = t & 1;
-    HIPCHK(launch_entropy(d, buf, r, mixed, s));
-    HIPCHK(launch_iter_init(d, r, threshold ? gamma0 : INFINITY, GAMMA_ADAPT, s));
-    queue_rounds(t, r, buf, threshold ? QUEUED_ROUNDS : 1);
-    queue_tail(t, r, buf);
+    bool any_last = false;
+    for (size_t k = 0; k < ps.size(); ++k) any_last |= (ps[k] - t == 1 && t < limits[k]);
+    if (any_last) HIPCHK(launch_last(b, t, s));
+    if (b.p_max - t < 2) return;
+    HIPCHK(launch_entropy(b, t, s));
+    HIPCHK(launch_iter_init(b, t, threshold ? gamma0 : INFINITY, GAMMA_ADAPT, s));
+    queue_rounds(t, threshold ? QUEUED_ROUNDS : 1);
+    queue_tail(t);
   }
 
-  Ctl read_ctl() {
+  // Threshold rounds of iteration tf of a data set (a batch of one) that
+  // halted because the queued rounds did not finish it, then its tail.
+  Ctl finish_halted(Ctl* ctl_dev, int tf, int p) {
+    HIPCHK(launch_resume(b, s));
+    Ctl c{};
+    for (int extra = 0;; ++extra) {
+      pair(tf, full_band(pl));
+      HIPCHK(launch_score(b, tf, full_band(pl), gmult, 0, s));
+      c = read_ctl(ctl_dev);
+      if (c.status != ST_OK || c.done) break;
+      if (extra > p - tf + 8) throw HipFail{hipErrorUnknown, "threshold rounds did not terminate", __LINE__};
+    }
+    if (c.status == ST_OK) queue_tail(tf);
+    return c;
+  }
+
+  Ctl read_ctl(Ctl* ctl_dev) {
     Ctl c;
-    HIPCHK(hipMemcpyAsync(&c, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&c, ctl_dev, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return c;
   }
+
+  // Iterations [t0, limit) of a batch of one, resuming halted iterations in
+  // place.  Returns the final control block.
+  Ctl drive_one(Ctl* ctl_dev, int t0, int limit, int p) {
+    int t = t0;
+    Ctl c{};
+    while (t < limit) {
+      for (int q = 0; q < SYNC_EVERY && t < limit; ++q, ++t) queue_iteration(t);
+      c = read_ctl(ctl_dev);
+      if (c.status != ST_OK) return c;
+      if (c.halt && c.halt_iter >= 0) {
+        // iteration halt_iter needed more threshold rounds than were queued;
+        // every launch queued after it returned at once, so its state is intact.
+        const int tf = c.halt_iter;
+        c = finish_halted(ctl_dev, tf, p);
+        if (c.status != ST_OK) return c;
+        t = tf + 1;
+      }
+    }
+    return read_ctl(ctl_dev);
+  }
 };
+
+void copy_results(const Dev& d, const Ctl& c, int64_t n, lingam_result* out, hipStream_t s) {
+  const size_t P = (size_t)d.p, pp = P * P;
+  std::vector<int32_t> order(P);
+  HIPCHK(hipMemcpyAsync(order.data(), d.order, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+  if (out->T) HIPCHK(hipMemcpyAsync(out->T, d.Tall, sizeof(double) * pp, hipMemcpyDeviceToHost, s));
+  if (out->T_state) HIPCHK(hipMemcpyAsync(out->T_state, d.Tstate, pp, hipMemcpyDeviceToHost, s));
+  if (out->H) HIPCHK(hipMemcpyAsync(out->H, d.Hall, sizeof(double) * pp, hipMemcpyDeviceToHost, s));
+  if (out->T_err_bound)
+    HIPCHK(hipMemcpyAsync(out->T_err_bound, d.Terr, sizeof(double) * pp, hipMemcpyDeviceToHost, s));
+  if (out->M && d.rec > 0)
+    HIPCHK(hipMemcpyAsync(out->M, d.Mrec, sizeof(double) * pp * d.rec, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::memcpy(out->order, order.data(), sizeof(int32_t) * P);
+  out->pairs_evaluated = c.pairs_evaluated;
+  out->pair_samples = c.pairs_evaluated * (uint64_t)n;
+  out->pairs_computed = c.pairs_computed;
+  out->threshold_rounds = c.rounds_total;
+  out->bands = c.bands_total;
+  int it = 0;
+  for (size_t k = 0; k < P; ++k) if (order[k] >= 0) ++it;
+  out->iterations = it;
+  if (c.status != ST_OK) {
+    out->bad_i = c.bad_i;
+    out->bad_j = c.bad_j;
+    out->status = c.status == ST_NONFINITE ? LINGAM_E_NONFINITE
+                : c.status == ST_DEGENERATE ? LINGAM_E_DEGENERATE : LINGAM_E_INVALID;
+  }
+}
+
+lingam_status status_from(const HipFail& e) {
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s failed: %s (line %d)", e.what, hipGetErrorString(e.err), e.line);
+  g_last_error = buf;
+  return e.err == hipErrorOutOfMemory ? LINGAM_E_NOMEM : LINGAM_E_DEVICE;
+}
+
+void set_error_text(lingam_status st, const lingam_result* out) {
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "%s (variables %d, %d)", lingam_status_string(st), out->bad_i, out->bad_j);
+  g_last_error = buf;
+}
 
 }  // namespace
 
@@ -304,7 +484,7 @@ uint64_t lingam_workspace_size(int64_t n, int64_t p, const lingam_opts* o) {
   b += 2 * pp * 8 + 2 * P * 8;          // rounding bounds: per test, per score record, eH, eT
   b += (uint64_t)op.record_M_iters * pp * 8;
   if (!op.x_on_device) b += P * (uint64_t)n * (op.x_dtype == 1 ? 4 : 8);
-  b += sizeof(Ctl);
+  b += sizeof(Ctl) + sizeof(Dev);
   return b;
 }
 
@@ -335,169 +515,69 @@ lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam
     timer.on = o.profile != 0;
     f.o = o;
     f.s = os.s;
-    f.p = (int)p;
-    f.n = n;
-    f.mixed = o.precision == LINGAM_PREC_MIXED;
+    const bool mixed = o.precision == LINGAM_PREC_MIXED;
     f.threshold = o.use_threshold != 0;
     f.gamma0 = o.gamma0 > 0 ? o.gamma0 : 0.0;  // 0 = adaptive
     f.gmult = o.gamma_mult > 1.0 ? o.gamma_mult : 4.0;
     f.pl = make_plan(n, o);
-    Dev& d = f.d;
-    d.p = (int)p;
-    d.n = n;
-    d.ldz = round_up(n, SUB);
-    const size_t P = (size_t)p, pp = P * P;
-    d.Z[0] = al.get<double>(P * d.ldz);
-    d.Z[1] = al.get<double>(P * d.ldz);
-    d.Sig[0] = al.get<double>(pp);
-    d.Sig[1] = al.get<double>(pp);
-    d.dsc[0] = al.get<double>(P);
-    d.dsc[1] = al.get<double>(P);
-    d.idx[0] = al.get<int32_t>(P);
-    d.idx[1] = al.get<int32_t>(P);
-    d.mixed = f.mixed ? 1 : 0;
-    d.H = al.get<double>(P);
-    d.eH = al.get<double>(P);
-    d.eT = al.get<double>(P);
-    d.Meps = al.get<double>(pp);
-    d.Terr = al.get<double>(pp);
-    d.M = al.get<double>(pp);
-    d.S = al.get<double>(P);
-    d.alive = al.get<uint8_t>(P);
-    d.alive_list = al.get<int32_t>(P);
-    d.complete = al.get<uint8_t>(P);
-    d.pend = al.get<uint8_t>(pp);
-    d.nchunk_max = f.pl.nchunk;
-    d.P = al.get<double>((size_t)f.pl.nchunk * pp * 4);
-    d.ctl = al.get<Ctl>(1);
-    d.order = al.get<int32_t>(P);
-    d.Tall = al.get<double>(pp);
-    d.Tstate = al.get<uint8_t>(pp);
-    d.Hall = al.get<double>(pp);
-    d.rec = o.record_M_iters;
-    d.Mrec = d.rec > 0 ? al.get<double>((size_t)d.rec * pp) : nullptr;
-    d.stats = al.get<double>(2 * P);
-    d.gram_slices_max = GRAM_SLICES_MAX;
-    d.Gp = al.get<double>((size_t)GRAM_SLICES_MAX * pp);
-    d.forced_len = o.forced_len;
-    int32_t* forced_dev = al.get<int32_t>(std::max<size_t>(1, (size_t)o.forced_len));
-    d.forced = forced_dev;
+    f.rec = o.record_M_iters;
+    const int limit = (o.max_roots > 0 && o.max_roots < p) ? o.max_roots : (int)p;
+    f.ps = {p};
+    f.limits = {limit};
 
-    const void* Xd = X;
+    Ctl* ctl = al.get<Ctl>(1);
+    Dev d = alloc_set(al, n, p, f.pl, o, mixed, ctl);
+    d.limit = limit;
     if (!o.x_on_device) {
-      const size_t bytes = P * (size_t)n * (o.x_dtype == 1 ? 4 : 8);
+      const size_t bytes = (size_t)p * (size_t)n * (o.x_dtype == 1 ? 4 : 8);
       void* xb = al.get<uint8_t>(bytes);
       HIPCHK(hipMemcpyAsync(xb, X, bytes, hipMemcpyHostToDevice, f.s));
-      Xd = xb;
+      d.X = xb;
+    } else {
+      d.X = X;
     }
-    if (o.forced_len > 0)
-      HIPCHK(hipMemcpyAsync(forced_dev, o.forced_order, sizeof(int32_t) * o.forced_len, hipMemcpyHostToDevice, f.s));
-    {
-      std::vector<int32_t> iota((size_t)p);
-      for (int64_t k = 0; k < p; ++k) iota[(size_t)k] = (int32_t)k;
-      HIPCHK(hipMemcpyAsync(d.idx[0], iota.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, f.s));
-      HIPCHK(hipStreamSynchronize(f.s));  // iota is a host temporary
-    }
+    Dev* dd = al.get<Dev>(1);
+    HIPCHK(hipMemcpyAsync(dd, &d, sizeof(Dev), hipMemcpyHostToDevice, f.s));
+    std::vector<int32_t> iota((size_t)p);
+    for (int64_t k = 0; k < p; ++k) iota[(size_t)k] = (int32_t)k;
+    init_set(d, o, limit, f.s, iota);
     Ctl c0;
     std::memset(&c0, 0, sizeof(c0));
     c0.halt_iter = -1;
     c0.root = -1;
     c0.bad_i = c0.bad_j = -1;
-    HIPCHK(hipMemcpyAsync(d.ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, f.s));
-    // fills by kernel (no memset nodes, so the sequence stays graph-capturable)
-    HIPCHK(launch_fill(d.Z[1], (int64_t)(P * d.ldz), 0.0, f.s));
-    HIPCHK(launch_fill(d.M, (int64_t)pp, NAN, f.s));
-    HIPCHK(launch_fill_u8(d.pend, (int64_t)pp, 0, f.s));
-    HIPCHK(launch_fill(d.Tall, (int64_t)pp, NAN, f.s));
-    HIPCHK(launch_fill_u8(d.Tstate, (int64_t)pp, 0, f.s));
-    HIPCHK(launch_fill(d.Hall, (int64_t)pp, NAN, f.s));
-    HIPCHK(launch_fill(d.Terr, (int64_t)pp, NAN, f.s));
-    if (d.Mrec) HIPCHK(launch_fill(d.Mrec, (int64_t)d.rec * (int64_t)pp, NAN, f.s));
-    HIPCHK(launch_fill_u8(reinterpret_cast<uint8_t*>(d.order), (int64_t)(4 * P), 0xff, f.s));
+    HIPCHK(hipMemcpyAsync(ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, f.s));
+    HIPCHK(hipStreamSynchronize(f.s));  // host temporaries (d, iota, c0) are no longer needed
+
+    f.b.dd = dd;
+    f.b.count = 1;
+    f.b.one = d;
+    f.b.p_max = (int)p;
+    f.b.n_max = n;
+    f.b.nchunk_max = d.nchunk;
+    f.b.gram_slices_max = GRAM_SLICES_MAX;
+    f.b.mixed = mixed ? 1 : 0;
 
     HIPCHK(hipEventCreate(&ev0));
     HIPCHK(hipEventCreate(&ev1));
     HIPCHK(hipEventRecord(ev0, f.s));
-
     // a1 + a2: normalise once, covariance once (Alg. 3)
-    HIPCHK(launch_standardize(Xd, o.x_dtype, o.layout, n, (int)p, d, f.s));
-    HIPCHK(launch_gram(d, 0, (int)p, f.s));
-
-    const int limit = (o.max_roots > 0 && o.max_roots < p) ? o.max_roots : (int)p;
-    int t = 0;  // next iteration to queue
-    Ctl c{};
-    while (t < limit) {
-      // queue up to SYNC_EVERY iterations without waiting on the device
-      for (int q = 0; q < SYNC_EVERY && t < limit; ++q, ++t) {
-        if ((int)p - t == 1) {
-          HIPCHK(launch_last(d, t & 1, t, f.s));
-        } else {
-          f.queue_iteration(t);
-        }
-      }
-      c = f.read_ctl();
-      if (c.status != ST_OK) break;
-      if (c.halt && c.halt_iter >= 0) {
-        // iteration halt_iter needed more threshold rounds than were queued;
-        // every launch queued after it returned at once, so its state is intact.
-        const int tf = c.halt_iter;
-        const int rf = (int)p - tf, buf = tf & 1;
-        HIPCHK(launch_resume(d, f.s));
-        for (int extra = 0;; ++extra) {
-          f.pair(buf, full_band(rf, f.pl));
-          HIPCHK(launch_score(d, buf, full_band(rf, f.pl), 1, tf, f.gmult, 0, f.s));
-          c = f.read_ctl();
-          if (c.status != ST_OK || c.done) break;
-          if (extra > rf + 8) throw HipFail{hipErrorUnknown, "threshold rounds did not terminate", __LINE__};
-        }
-        if (c.status != ST_OK) break;
-        f.queue_tail(tf, rf, buf);
-        t = tf + 1;
-      }
-    }
+    HIPCHK(launch_standardize(f.b, f.s));
+    HIPCHK(launch_gram(f.b, 0, 0, f.s));
+    Ctl c = f.drive_one(ctl, 0, limit, (int)p);
     HIPCHK(hipEventRecord(ev1, f.s));
-    c = f.read_ctl();
-
-    // results
-    std::vector<int32_t> order((size_t)p);
-    HIPCHK(hipMemcpyAsync(order.data(), d.order, sizeof(int32_t) * P, hipMemcpyDeviceToHost, f.s));
-    if (out->T) HIPCHK(hipMemcpyAsync(out->T, d.Tall, sizeof(double) * pp, hipMemcpyDeviceToHost, f.s));
-    if (out->T_state) HIPCHK(hipMemcpyAsync(out->T_state, d.Tstate, pp, hipMemcpyDeviceToHost, f.s));
-    if (out->H) HIPCHK(hipMemcpyAsync(out->H, d.Hall, sizeof(double) * pp, hipMemcpyDeviceToHost, f.s));
-    if (out->T_err_bound)
-      HIPCHK(hipMemcpyAsync(out->T_err_bound, d.Terr, sizeof(double) * pp, hipMemcpyDeviceToHost, f.s));
-    if (out->M && d.rec > 0)
-      HIPCHK(hipMemcpyAsync(out->M, d.Mrec, sizeof(double) * pp * d.rec, hipMemcpyDeviceToHost, f.s));
-    HIPCHK(hipStreamSynchronize(f.s));
-    std::memcpy(out->order, order.data(), sizeof(int32_t) * P);
+    copy_results(d, c, n, out, f.s);
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) out->seconds_device = ms * 1e-3;
-    out->pairs_evaluated = c.pairs_evaluated;
-    out->pair_samples = c.pairs_evaluated * (uint64_t)n;
-    out->pairs_computed = c.pairs_computed;
-    out->threshold_rounds = c.rounds_total;
     if (timer.on) {
       out->seconds_pair_kernel = timer.total_seconds();
       out->pair_kernel_launches = timer.launches;
     }
-    out->bands = c.bands_total;
-    int it = 0;
-    for (int64_t k = 0; k < p; ++k) if (order[(size_t)k] >= 0) ++it;
-    out->iterations = it;
-    if (c.status != ST_OK) {
-      out->bad_i = c.bad_i;
-      out->bad_j = c.bad_j;
-      st = c.status == ST_NONFINITE ? LINGAM_E_NONFINITE
-           : c.status == ST_DEGENERATE ? LINGAM_E_DEGENERATE : LINGAM_E_INVALID;
-      char buf[160];
-      std::snprintf(buf, sizeof buf, "%s (variables %d, %d)", lingam_status_string(st), c.bad_i, c.bad_j);
-      g_last_error = buf;
-    }
+    st = (lingam_status)out->status;
+    if (st != LINGAM_OK) set_error_text(st, out);
   } catch (const HipFail& e) {
-    char buf[256];
-    std::snprintf(buf, sizeof buf, "%s failed: %s (line %d)", e.what, hipGetErrorString(e.err), e.line);
-    g_last_error = buf;
-    st = e.err == hipErrorOutOfMemory ? LINGAM_E_NOMEM : LINGAM_E_DEVICE;
+    st = status_from(e);
+    out->status = st;
   }
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
@@ -505,11 +585,190 @@ lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam
   return st;
 }
 
-lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, const lingam_opts* o,
+lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, const lingam_opts* opts,
                                      lingam_result* outs) {
-  (void)count; (void)sets; (void)o; (void)outs;
-  g_last_error = "batched execution is not available in this build";
-  return LINGAM_E_UNSUPPORTED;
+  const auto wall0 = std::chrono::steady_clock::now();
+  g_last_error.clear();
+  lingam_opts o;
+  if (opts) o = *opts; else lingam_opts_default(&o);
+  if (count < 1 || !sets || !outs) return fail(LINGAM_E_INVALID, "empty batch or NULL arrays");
+  if (count > 65535) return fail(LINGAM_E_INVALID, "at most 65535 data sets per batch");
+  lingam_status st = validate_opts(o);
+  if (st != LINGAM_OK) return st;
+  if (o.forced_len > 0 || o.record_M_iters > 0)
+    return fail(LINGAM_E_UNSUPPORTED, "forced_order and record_M_iters are not available in batches");
+  for (int k = 0; k < count; ++k) {
+    const lingam_dataset& ds = sets[k];
+    if (!ds.X) return fail(LINGAM_E_INVALID, "data set with X == NULL");
+    if (!outs[k].order) return fail(LINGAM_E_INVALID, "result->order is NULL");
+    const int64_t nk = ds.sample_idx ? ds.n_idx : ds.n;
+    st = validate_shape(nk, ds.p);
+    if (st != LINGAM_OK) return st;
+    if (ds.sample_idx) {
+      if (ds.n < 1) return fail(LINGAM_E_INVALID, "bootstrap base with n < 1");
+      if (o.x_dtype != 0 || o.layout != LINGAM_LAYOUT_VAR_MAJOR)
+        return fail(LINGAM_E_UNSUPPORTED, "bootstrap data sets need a binary64 p x n base");
+      for (int64_t i = 0; i < ds.n_idx; ++i)
+        if (ds.sample_idx[i] < 0 || ds.sample_idx[i] >= ds.n)
+          return fail(LINGAM_E_INVALID, "bootstrap sample index out of range");
+    }
+  }
+  for (int k = 0; k < count; ++k) reset_result(&outs[k], sets[k].p, 0);
+
+  Allocs al;
+  OwnedStream os;
+  PairTimer timer;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  try {
+    if (o.device >= 0) HIPCHK(hipSetDevice(o.device));
+    if (o.stream) {
+      os.s = (hipStream_t)o.stream;
+    } else {
+      HIPCHK(hipStreamCreate(&os.s));
+      os.owned = true;
+    }
+    Fit f;
+    f.timer = &timer;
+    timer.on = o.profile != 0;
+    f.o = o;
+    f.s = os.s;
+    const bool mixed = o.precision == LINGAM_PREC_MIXED;
+    f.threshold = o.use_threshold != 0;
+    f.gamma0 = o.gamma0 > 0 ? o.gamma0 : 0.0;
+    f.gmult = o.gamma_mult > 1.0 ? o.gamma_mult : 4.0;
+    int64_t p_max = 0, n_max = 0;
+    for (int k = 0; k < count; ++k) {
+      p_max = std::max(p_max, sets[k].p);
+      n_max = std::max(n_max, sets[k].sample_idx ? sets[k].n_idx : sets[k].n);
+    }
+    f.pl = make_plan(n_max, o);  // the chunk length is the same for every data set
+    Ctl* ctls = al.get<Ctl>((size_t)count);
+    std::vector<Dev> devs((size_t)count);
+    f.ps.resize((size_t)count);
+    f.limits.resize((size_t)count);
+    // bases of bootstrap sets are uploaded once each
+    std::vector<std::pair<const void*, const double*>> bases;
+    std::vector<int32_t> iota((size_t)p_max);
+    for (int64_t k = 0; k < p_max; ++k) iota[(size_t)k] = (int32_t)k;
+    int nchunk_max = 1;
+    for (int k = 0; k < count; ++k) {
+      const lingam_dataset& ds = sets[k];
+      const int64_t nk = ds.sample_idx ? ds.n_idx : ds.n, pk = ds.p;
+      const int limit = (o.max_roots > 0 && o.max_roots < pk) ? o.max_roots : (int)pk;
+      Dev d = alloc_set(al, nk, pk, f.pl, o, mixed, ctls + k);
+      d.limit = limit;
+      if (ds.sample_idx) {
+        const double* base = nullptr;
+        for (auto& bp : bases) if (bp.first == ds.X) base = bp.second;
+        if (!base) {
+          if (o.x_on_device) {
+            base = (const double*)ds.X;
+          } else {
+            double* xb = al.get<double>((size_t)pk * (size_t)ds.n);
+            HIPCHK(hipMemcpyAsync(xb, ds.X, sizeof(double) * pk * ds.n, hipMemcpyHostToDevice, f.s));
+            base = xb;
+          }
+          bases.push_back({ds.X, base});
+        }
+        int64_t* idx_dev = al.get<int64_t>((size_t)ds.n_idx);
+        HIPCHK(hipMemcpyAsync(idx_dev, ds.sample_idx, sizeof(int64_t) * ds.n_idx, hipMemcpyHostToDevice, f.s));
+        double* xg = al.get<double>((size_t)pk * (size_t)nk);
+        HIPCHK(launch_gather(base, ds.n, pk, idx_dev, nk, xg, f.s));
+        d.X = xg;
+        d.x_dtype = 0;
+        d.layout = 0;
+      } else if (!o.x_on_device) {
+        const size_t bytes = (size_t)pk * (size_t)nk * (o.x_dtype == 1 ? 4 : 8);
+        void* xb = al.get<uint8_t>(bytes);
+        HIPCHK(hipMemcpyAsync(xb, ds.X, bytes, hipMemcpyHostToDevice, f.s));
+        d.X = xb;
+      } else {
+        d.X = ds.X;
+      }
+      init_set(d, o, limit, f.s, iota);
+      devs[(size_t)k] = d;
+      f.ps[(size_t)k] = pk;
+      f.limits[(size_t)k] = limit;
+      nchunk_max = std::max(nchunk_max, d.nchunk);
+    }
+    Dev* dd = al.get<Dev>((size_t)count);
+    HIPCHK(hipMemcpyAsync(dd, devs.data(), sizeof(Dev) * count, hipMemcpyHostToDevice, f.s));
+    std::vector<Ctl> c0((size_t)count);
+    std::memset(c0.data(), 0, sizeof(Ctl) * count);
+    for (auto& c : c0) {
+      c.halt_iter = -1;
+      c.root = -1;
+      c.bad_i = c.bad_j = -1;
+    }
+    HIPCHK(hipMemcpyAsync(ctls, c0.data(), sizeof(Ctl) * count, hipMemcpyHostToDevice, f.s));
+    HIPCHK(hipStreamSynchronize(f.s));
+
+    f.b.dd = dd;
+    f.b.count = count;
+    f.b.p_max = (int)p_max;
+    f.b.n_max = n_max;
+    f.b.nchunk_max = nchunk_max;
+    f.b.gram_slices_max = GRAM_SLICES_MAX;
+    f.b.mixed = mixed ? 1 : 0;
+    int limit_max = 0;
+    for (int l : f.limits) limit_max = std::max(limit_max, l);
+
+    HIPCHK(hipEventCreate(&ev0));
+    HIPCHK(hipEventCreate(&ev1));
+    HIPCHK(hipEventRecord(ev0, f.s));
+    HIPCHK(launch_standardize(f.b, f.s));
+    HIPCHK(launch_gram(f.b, 0, 0, f.s));
+    // every data set steps through its iterations together; one that halts
+    // (not enough threshold rounds queued, or an error) sits out from then on
+    std::vector<Ctl> cs((size_t)count);
+    for (int t = 0; t < limit_max;) {
+      for (int q = 0; q < SYNC_EVERY && t < limit_max; ++q, ++t) f.queue_iteration(t);
+      HIPCHK(hipMemcpyAsync(cs.data(), ctls, sizeof(Ctl) * count, hipMemcpyDeviceToHost, f.s));
+      HIPCHK(hipStreamSynchronize(f.s));
+    }
+    // stragglers: finish each one alone, from the iteration that halted
+    for (int k = 0; k < count; ++k) {
+      if (cs[(size_t)k].status != ST_OK || !(cs[(size_t)k].halt && cs[(size_t)k].halt_iter >= 0)) continue;
+      Fit g = f;
+      g.b.dd = dd + k;
+      g.b.count = 1;
+      g.b.one = devs[(size_t)k];
+      g.b.p_max = (int)sets[k].p;
+      g.b.n_max = devs[(size_t)k].n;
+      g.b.nchunk_max = devs[(size_t)k].nchunk;
+      g.ps = {sets[k].p};
+      g.limits = {f.limits[(size_t)k]};
+      const int tf = cs[(size_t)k].halt_iter;
+      Ctl c = g.finish_halted(ctls + k, tf, (int)sets[k].p);
+      if (c.status == ST_OK) g.drive_one(ctls + k, tf + 1, f.limits[(size_t)k], (int)sets[k].p);
+    }
+    HIPCHK(hipEventRecord(ev1, f.s));
+    HIPCHK(hipMemcpyAsync(cs.data(), ctls, sizeof(Ctl) * count, hipMemcpyDeviceToHost, f.s));
+    HIPCHK(hipStreamSynchronize(f.s));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev0, ev1);
+    st = LINGAM_OK;
+    for (int k = 0; k < count; ++k) {
+      copy_results(devs[(size_t)k], cs[(size_t)k], devs[(size_t)k].n, &outs[k], f.s);
+      outs[k].seconds_device = ms * 1e-3;
+      if (timer.on) {
+        outs[k].seconds_pair_kernel = timer.total_seconds();
+        outs[k].pair_kernel_launches = timer.launches;
+      }
+      if (outs[k].status != LINGAM_OK && st == LINGAM_OK) {
+        st = (lingam_status)outs[k].status;
+        set_error_text(st, &outs[k]);
+      }
+    }
+  } catch (const HipFail& e) {
+    st = status_from(e);
+    for (int k = 0; k < count; ++k) outs[k].status = st;
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+  for (int k = 0; k < count; ++k) outs[k].seconds_total = wall;
+  return st;
 }
 
 }  // extern "C"

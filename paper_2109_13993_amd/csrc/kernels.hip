@@ -32,6 +32,11 @@
 
 namespace lingam {
 
+// Kernel arguments naming the data sets of a launch: a batch of one passes
+// its descriptor by value (no extra dependent load before a kernel can find
+// its buffers); a larger batch passes the device array.
+#define DEVS(b) ((b).count == 1 ? nullptr : (b).dd), (b).one
+
 namespace {
 
 // Eq. (HApp) constants as printed; H(nu) = (1 + log 2 pi) / 2.
@@ -41,6 +46,9 @@ constexpr double BETA = 0.37457;
 constexpr double HNU = 1.4189385332046727418;
 constexpr double LN2 = 0.69314718055994530942;
 constexpr float LOG2E_F = 1.44269504088896340736f;
+
+// Variables left in data set d at iteration t (0 once its iterations are done).
+__device__ __forceinline__ int rows_left(const Dev& d, int t) { return t < d.limit ? d.p - t : 0; }
 
 __device__ __forceinline__ bool halted(const Ctl* c) {
   return __atomic_load_n(&c->halt, __ATOMIC_RELAXED) != 0;
@@ -144,12 +152,10 @@ __device__ __forceinline__ double happ_from_sums(double s_lc, double s_g, double
 // a1: NormalizeData
 // ============================================================================
 template <typename T, int LAYOUT>
-__global__ __launch_bounds__(256) void k_standardize(const T* __restrict__ X, int64_t n, int p,
-                                                     double* __restrict__ Z, int64_t ldz,
-                                                     Ctl* ctl, double* stats) {
+__device__ void standardize_row(const T* __restrict__ X, int64_t n, int p, int i, double* __restrict__ Z,
+                                int64_t ldz, Ctl* ctl, double* stats) {
   __shared__ double sh[4];
   __shared__ int shi[4];
-  const int i = blockIdx.x;
   auto load = [&](int64_t k) -> double {
     return LAYOUT == 0 ? (double)X[(int64_t)i * n + k] : (double)X[k * (int64_t)p + i];
   };
@@ -188,17 +194,48 @@ __global__ __launch_bounds__(256) void k_standardize(const T* __restrict__ X, in
   }
 }
 
-hipError_t launch_standardize(const void* X, int x_dtype, int layout, int64_t n, int p,
-                              const Dev& d, hipStream_t s) {
-  dim3 g(p), b(256);
-  if (x_dtype == 0 && layout == 0)
-    hipLaunchKernelGGL((k_standardize<double, 0>), g, b, 0, s, (const double*)X, n, p, d.Z[0], d.ldz, d.ctl, d.stats);
-  else if (x_dtype == 0)
-    hipLaunchKernelGGL((k_standardize<double, 1>), g, b, 0, s, (const double*)X, n, p, d.Z[0], d.ldz, d.ctl, d.stats);
-  else if (layout == 0)
-    hipLaunchKernelGGL((k_standardize<float, 0>), g, b, 0, s, (const float*)X, n, p, d.Z[0], d.ldz, d.ctl, d.stats);
+// One work-group per row (blockIdx.x) of data set blockIdx.z.
+__device__ __forceinline__ void k_standardize_body(const Dev& d) {
+  const int i = blockIdx.x;
+  if (i >= d.p) return;
+  if (d.x_dtype == 0 && d.layout == 0)
+    standardize_row<double, 0>((const double*)d.X, d.n, d.p, i, d.Z[0], d.ldz, d.ctl, d.stats);
+  else if (d.x_dtype == 0)
+    standardize_row<double, 1>((const double*)d.X, d.n, d.p, i, d.Z[0], d.ldz, d.ctl, d.stats);
+  else if (d.layout == 0)
+    standardize_row<float, 0>((const float*)d.X, d.n, d.p, i, d.Z[0], d.ldz, d.ctl, d.stats);
   else
-    hipLaunchKernelGGL((k_standardize<float, 1>), g, b, 0, s, (const float*)X, n, p, d.Z[0], d.ldz, d.ctl, d.stats);
+    standardize_row<float, 1>((const float*)d.X, d.n, d.p, i, d.Z[0], d.ldz, d.ctl, d.stats);
+}
+
+__global__ __launch_bounds__(256) void k_standardize(const Dev* __restrict__ devs, const Dev one) {
+  if (devs)
+    k_standardize_body(devs[blockIdx.z]);
+  else
+    k_standardize_body(one);
+}
+
+hipError_t launch_standardize(const Batch& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_standardize, dim3(b.p_max, 1, b.count), dim3(256), 0, s, DEVS(b));
+  return hipGetLastError();
+}
+
+// Bootstrap resample: out[i][k] = X[i][idx[k]] for the p rows of a p x n_src
+// binary64 matrix (row = variable).
+__global__ __launch_bounds__(256) void k_gather(const double* __restrict__ X, int64_t n_src,
+                                                const int64_t* __restrict__ idx, int64_t n_idx,
+                                                double* __restrict__ out) {
+  const int i = blockIdx.y;
+  for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < n_idx; k += (int64_t)gridDim.x * 256) {
+    const int64_t j = idx[k];
+    out[(int64_t)i * n_idx + k] = (j >= 0 && j < n_src) ? X[(int64_t)i * n_src + j] : __builtin_nan("");
+  }
+}
+
+hipError_t launch_gather(const double* X, int64_t n_src, int64_t p, const int64_t* idx, int64_t n_idx,
+                         double* out, hipStream_t s) {
+  const int xb = (int)std::min<int64_t>(64, (n_idx + 255) / 256);
+  hipLaunchKernelGGL(k_gather, dim3(std::max(xb, 1), (unsigned)p), dim3(256), 0, s, X, n_src, idx, n_idx, out);
   return hipGetLastError();
 }
 
@@ -209,19 +246,42 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int GT = 32;   // output tile (GT x GT) per work-group, 4 waves of 16 x 16
 constexpr int GK = 64;   // samples per LDS stage
 
+// Sample slices of the split Gram for r rows and n samples: enough work-
+// groups to fill the device, each slice at least four LDS stages long.
+__host__ __device__ inline int gram_slices(int r, int64_t n, int max_slices) {
+  const int nt = (r + GT - 1) / GT;
+  const int tiles = nt * (nt + 1) / 2;
+  int sl = (2048 + tiles - 1) / tiles;
+  const int64_t stages = (n + GK - 1) / GK;
+  const int64_t cap = stages / 4 > 1 ? stages / 4 : 1;
+  if ((int64_t)sl > cap) sl = (int)cap;
+  if (sl > max_slices) sl = max_slices;
+  return sl < 1 ? 1 : sl;
+}
+
 // Partial Gram of one sample slice: Gp[slice][i][j] = sum_{k in slice} z_i[k] z_j[k]
 // for the upper-triangular 32 x 32 tile given by blockIdx.x (i <= j).  Each
 // LDS stage is summed by the matrix cores into a fresh accumulator and then
 // added into a Kahan-compensated total; the next stage is fetched into
 // registers while the current one is multiplied.
-__global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__ Z, int64_t ldz,
-                                                      int64_t n, int r, int64_t slice_len,
-                                                      double* __restrict__ Gp, int ldg,
-                                                      const Ctl* ctl) {
-  if (halted(ctl)) return;
+// Grid: (tiles, slices, data sets), sized for the largest data set; each
+// data set uses its own tile and slice counts (the same as when it runs
+// alone), and the surplus work-groups return.
+__device__ __forceinline__ void k_gram_partial_body(const Dev& d, int buf, int t) {
+  const int r = rows_left(d, t);
+  if (r < 1 || halted(d.ctl)) return;
+  const double* __restrict__ Z = d.Z[buf];
+  const int64_t ldz = d.ldz, n = d.n;
+  double* __restrict__ Gp = d.Gp;
+  const int ldg = d.p;
+  const int nsl = gram_slices(r, n, d.gram_slices_max);  // this data set's own split
+  if ((int)blockIdx.y >= nsl) return;
+  const int64_t stages = (n + GK - 1) / GK;
+  const int64_t slice_len = (stages + nsl - 1) / nsl * GK;
   __shared__ double As[GT][GK + 1];
   __shared__ double Bs[GT][GK + 1];
   const int nt = (r + GT - 1) / GT;
+  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
   int ti = 0, rem = blockIdx.x;
   while (rem >= nt - ti) { rem -= nt - ti; ++ti; }
   const int tj = ti + rem;
@@ -283,15 +343,27 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__
   }
 }
 
+__global__ __launch_bounds__(256) void k_gram_partial(const Dev* __restrict__ devs, const Dev one, int buf, int t) {
+  if (devs)
+    k_gram_partial_body(devs[blockIdx.z], buf, t);
+  else
+    k_gram_partial_body(one, buf, t);
+}
+
 // Sum the slices in a fixed order, scale by 1/(n-1), mirror, and set the row
 // scales d_i = 1/sqrt(G_ii).
-__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ Gp, int ldg, int nslice,
-                                                     int r, double n, double* __restrict__ Sig,
-                                                     double* __restrict__ dsc, const Ctl* ctl) {
-  if (halted(ctl)) return;
+__device__ __forceinline__ void k_gram_reduce_body(const Dev& d, int buf, int t) {
+  const int r = rows_left(d, t);
+  if (r < 1 || halted(d.ctl)) return;
+  const int nslice = gram_slices(r, d.n, d.gram_slices_max);
+  const double* __restrict__ Gp = d.Gp;
+  double* __restrict__ Sig = d.Sig[buf];
+  double* __restrict__ dsc = d.dsc[buf];
+  const int ldg = d.p;
+  const double n = (double)d.n;
   const int i = blockIdx.y;
   const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j < i || j >= r) return;
+  if (i >= r || j < i || j >= r) return;
   double sum = 0.0;
   for (int q = 0; q < nslice; ++q) sum += Gp[((int64_t)q * ldg + i) * ldg + j];
   const double val = sum / (n - 1.0);
@@ -300,26 +372,23 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
   if (i == j) dsc[i] = 1.0 / sqrt(val);
 }
 
-int gram_slices(int r, int64_t n, int max_slices) {
-  const int nt = (r + GT - 1) / GT;
-  const int tiles = nt * (nt + 1) / 2;
-  int sl = (2048 + tiles - 1) / tiles;
-  const int64_t stages = (n + GK - 1) / GK;
-  sl = (int)std::min<int64_t>(sl, std::max<int64_t>(1, stages / 4));
-  return std::max(1, std::min(sl, max_slices));
+__global__ __launch_bounds__(256) void k_gram_reduce(const Dev* __restrict__ devs, const Dev one, int buf, int t) {
+  if (devs)
+    k_gram_reduce_body(devs[blockIdx.z], buf, t);
+  else
+    k_gram_reduce_body(one, buf, t);
 }
 
-hipError_t launch_gram(const Dev& d, int buf, int r, hipStream_t s) {
+// Gram of the r = p - t rows of buffer buf of every data set.
+hipError_t launch_gram(const Batch& b, int buf, int t, hipStream_t s) {
+  const int r = b.p_max - t;
+  if (r < 1) return hipSuccess;
   const int nt = (r + GT - 1) / GT;
-  const int sl = gram_slices(r, d.n, d.gram_slices_max);
-  const int64_t stages = (d.n + GK - 1) / GK;
-  const int64_t slice_len = (stages + sl - 1) / sl * GK;
-  hipLaunchKernelGGL(k_gram_partial, dim3(nt * (nt + 1) / 2, sl), dim3(256), 0, s, d.Z[buf], d.ldz, d.n, r,
-                     slice_len, d.Gp, d.p, d.ctl);
+  hipLaunchKernelGGL(k_gram_partial, dim3(nt * (nt + 1) / 2, b.gram_slices_max, b.count), dim3(256), 0, s,
+                     DEVS(b), buf, t);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((r + 255) / 256, r), dim3(256), 0, s, d.Gp, d.p, sl, r,
-                     (double)d.n, d.Sig[buf], d.dsc[buf], d.ctl);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((r + 255) / 256, r, b.count), dim3(256), 0, s, DEVS(b), buf, t);
   return hipGetLastError();
 }
 
@@ -327,14 +396,16 @@ hipError_t launch_gram(const Dev& d, int buf, int r, hipStream_t s) {
 // a3: per-variable entropy H(x_u), Eq. (HApp)
 // ============================================================================
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_entropy(const double* __restrict__ Z, int64_t ldz, int64_t n,
-                                                 const double* __restrict__ dsc,
-                                                 double* __restrict__ H, double* __restrict__ eH,
-                                                 const Ctl* ctl) {
-  if (halted(ctl)) return;
+__device__ __forceinline__ void k_entropy_body(const Dev& d, int t) {
+  const int r = rows_left(d, t);
+  if ((int)blockIdx.x >= r || r < 2 || halted(d.ctl)) return;
+  const int buf = t & 1;
+  const int64_t n = d.n;
+  double* __restrict__ H = d.H;
+  double* __restrict__ eH = d.eH;
   __shared__ double sh[4];
-  const double* z = Z + (int64_t)blockIdx.x * ldz;
-  const double dz = dsc[blockIdx.x];
+  const double* z = d.Z[buf] + (int64_t)blockIdx.x * d.ldz;
+  const double dz = d.dsc[buf][blockIdx.x];
   double lc = 0.0, g = 0.0;
   if constexpr (MIXED) {
     const float ca = -2.0f * LOG2E_F, cg = -0.5f * LOG2E_F;
@@ -356,12 +427,21 @@ __global__ __launch_bounds__(256) void k_entropy(const double* __restrict__ Z, i
   }
 }
 
-hipError_t launch_entropy(const Dev& d, int buf, int r, int mixed, hipStream_t s) {
-  if (mixed)
-    hipLaunchKernelGGL(k_entropy<true>, dim3(r), dim3(256), 0, s, d.Z[buf], d.ldz, d.n, d.dsc[buf], d.H, d.eH, d.ctl);
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_entropy(const Dev* __restrict__ devs, const Dev one, int t) {
+  if (devs)
+    k_entropy_body<MIXED>(devs[blockIdx.z], t);
   else
-    hipLaunchKernelGGL(k_entropy<false>, dim3(r), dim3(256), 0, s, d.Z[buf], d.ldz, d.n, d.dsc[buf], d.H, d.eH,
-                       d.ctl);
+    k_entropy_body<MIXED>(one, t);
+}
+
+hipError_t launch_entropy(const Batch& b, int t, hipStream_t s) {
+  const int r = b.p_max - t;
+  if (r < 2) return hipSuccess;
+  if (b.mixed)
+    hipLaunchKernelGGL(k_entropy<true>, dim3(r, 1, b.count), dim3(256), 0, s, DEVS(b), t);
+  else
+    hipLaunchKernelGGL(k_entropy<false>, dim3(r, 1, b.count), dim3(256), 0, s, DEVS(b), t);
   return hipGetLastError();
 }
 
@@ -371,9 +451,16 @@ hipError_t launch_entropy(const Dev& d, int buf, int r, int mixed, hipStream_t s
 // gamma0 > 0: that initial threshold in every iteration; gamma0 <= 0: adaptive,
 // `adapt` times the previous iteration's root score (the first iteration and a
 // zero previous score use 1e-6).
-__global__ void k_iter_init(double* M, uint8_t* pend, double* S, uint8_t* alive, uint8_t* complete,
-                            int32_t* alive_list, int r, int p, double gamma0, double adapt, Ctl* ctl) {
-  if (halted(ctl)) return;
+__device__ __forceinline__ void k_iter_init_body(const Dev& d, int t, double gamma0, double adapt) {
+  const int r = rows_left(d, t), p = d.p;
+  Ctl* ctl = d.ctl;
+  if (r < 2 || halted(ctl)) return;
+  double* M = d.M;
+  uint8_t* pend = d.pend;
+  double* S = d.S;
+  uint8_t* alive = d.alive;
+  uint8_t* complete = d.complete;
+  int32_t* alive_list = d.alive_list;
   const int64_t total = (int64_t)r * r;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -401,13 +488,19 @@ __global__ void k_iter_init(double* M, uint8_t* pend, double* S, uint8_t* alive,
   }
 }
 
-hipError_t launch_iter_init(const Dev& d, int r, double gamma0, double adapt, hipStream_t s) {
+__global__ void k_iter_init(const Dev* __restrict__ devs, const Dev one, int t, double gamma0, double adapt) {
+  if (devs)
+    k_iter_init_body(devs[blockIdx.z], t, gamma0, adapt);
+  else
+    k_iter_init_body(one, t, gamma0, adapt);
+}
+
+hipError_t launch_iter_init(const Batch& b, int t, double gamma0, double adapt, hipStream_t s) {
+  const int r = b.p_max - t;
+  if (r < 2) return hipSuccess;
   const int64_t total = (int64_t)r * r;
-  int blocks = (int)((total + 255) / 256);
-  if (blocks > 1024) blocks = 1024;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_iter_init, dim3(blocks), dim3(256), 0, s, d.M, d.pend, d.S, d.alive,
-                     d.complete, d.alive_list, r, d.p, gamma0, adapt, d.ctl);
+  int blocks = (int)std::min<int64_t>(std::max(8, 1024 / b.count), (total + 255) / 256);
+  hipLaunchKernelGGL(k_iter_init, dim3(std::max(blocks, 1), 1, b.count), dim3(256), 0, s, DEVS(b), t, gamma0, adapt);
   return hipGetLastError();
 }
 
@@ -461,12 +554,24 @@ constexpr int log2_of() { return NV <= 1 ? 0 : 1 + log2_of<NV / 2>(); }
 // issued before the current stage is computed, so one barrier per stage
 // suffices and the load latency hides behind the arithmetic.
 template <bool MIXED, int RG, int TPW, int PS>
-__global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(
-    const double* __restrict__ Z, int64_t ldz, int64_t n, const double* __restrict__ Sig,
-    const double* __restrict__ dsc, const double* __restrict__ M,
-    const uint8_t* __restrict__ alive, const int32_t* __restrict__ alive_list,
-    double* __restrict__ P, uint8_t* __restrict__ pend, const int32_t* __restrict__ idx, int p,
-    BandArgs a, Ctl* ctl) {
+__device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a) {
+  const int r = rows_left(d, t), p = d.p;
+  const int nb = (r + TB - 1) / TB;
+  a.ntb = min(a.ntb, nb - a.tb0);   // the band's blocks that exist for this data set
+  if (r < 2 || a.ntb <= 0) return;
+  const int buf = t & 1;
+  const double* __restrict__ Z = d.Z[buf];
+  const int64_t ldz = d.ldz, n = d.n;
+  const double* __restrict__ Sig = d.Sig[buf];
+  const double* __restrict__ dsc = d.dsc[buf];
+  const double* __restrict__ M = d.M;
+  const uint8_t* __restrict__ alive = d.alive;
+  const int32_t* __restrict__ alive_list = d.alive_list;
+  double* __restrict__ P = d.P;
+  uint8_t* __restrict__ pend = d.pend;
+  const int32_t* __restrict__ idx = d.idx[buf];
+  Ctl* ctl = d.ctl;
+  const int nchunk = d.nchunk;
   constexpr int WPR = TB / TPW;     // waves per row
   constexpr int NW = RG * WPR;      // waves per work-group
   constexpr int SPL = PS / 64;      // samples per lane and stage
@@ -492,13 +597,12 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(
   // contiguous eighth of the items (same chunk and target block, different
   // row groups) and its work-groups share the XCD's L2.
   const int nrg = (m + RG - 1) / RG;
-  const int items = nrg * a.ntb * a.nchunk;
+  const int items = nrg * a.ntb * nchunk;
   const int xcd = blockIdx.x % 8, per_xcd = gridDim.x / 8;
   const int ipx = (items + 7) / 8;
   const int lo = xcd * ipx, hi = min(items, lo + ipx);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int lane = threadIdx.x % 64;
-  const int r = a.r;
   for (int item = lo + (int)(blockIdx.x / 8); item < hi; item += per_xcd) {
   const int g = item % nrg;
   const int tb = (item / nrg) % a.ntb;
@@ -682,6 +786,17 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(
   }
 }
 
+// BATCH selects the descriptor source at compile time, so each instance
+// holds one copy of the (register-heavy) body.
+template <bool MIXED, int RG, int TPW, int PS, bool BATCH>
+__global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(const Dev* __restrict__ devs, const Dev one,
+                                                                   int t, BandArgs a) {
+  if constexpr (BATCH)
+    k_pair_band_body<MIXED, RG, TPW, PS>(devs[blockIdx.z], t, a);
+  else
+    k_pair_band_body<MIXED, RG, TPW, PS>(one, t, a);
+}
+
 // Work-group shapes of the pair kernel (results do not depend on them).
 // Dense bands (every variable still alive): 16 rows x 8 targets per wave,
 // so each staged target block is shared by 16 rows.  Sparse bands: one row
@@ -696,7 +811,7 @@ static int resident_groups() {
     int dev = 0, per_cu = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pair_band<MIXED, RG, TPW, PS>,
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pair_band<MIXED, RG, TPW, PS, false>,
                                                      64 * RG * (TB / TPW), 0) != hipSuccess ||
         per_cu < 1 || cus < 1) {
       per_cu = 1;
@@ -708,28 +823,34 @@ static int resident_groups() {
 }
 
 template <bool MIXED, int RG, int TPW, int PS>
-static void launch_pair_shape(const Dev& d, int buf, BandArgs a, hipStream_t s, int max_waves) {
-  a.nrg = (a.r + RG - 1) / RG;
-  // at most max_waves generations of resident work-groups; sparse bands use
-  // one, so no work-group waits for a slot only to find nothing to do
-  const int cap = std::max(8, max_waves * resident_groups<MIXED, RG, TPW, PS>());
-  const int G = std::min(a.ntb * a.nchunk * a.nrg, cap);  // items when every row is alive
+static void launch_pair_shape(const Batch& b, int t, const BandArgs& a, hipStream_t s, int max_waves) {
+  const int r = b.p_max - t;
+  const int nb = (r + TB - 1) / TB;
+  const int ntb = std::min(a.ntb, nb - a.tb0);
+  if (r < 2 || ntb <= 0) return;
+  const int nrg = (r + RG - 1) / RG;
+  // at most max_waves generations of resident work-groups over the batch;
+  // sparse bands use one, so no work-group waits for a slot only to find
+  // nothing to do
+  const int per_set = std::max(8, max_waves * resident_groups<MIXED, RG, TPW, PS>() / b.count);
+  const int G = std::min(ntb * b.nchunk_max * nrg, per_set);  // items when every row is alive
   const int grid = (G + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS>), dim3(grid), dim3(64 * RG * (TB / TPW)), 0, s, d.Z[buf],
-                     d.ldz, d.n, d.Sig[buf], d.dsc[buf], d.M, d.alive, d.alive_list, d.P, d.pend, d.idx[buf],
-                     d.p, a, d.ctl);
+  const dim3 g(grid, 1, b.count), blk(64 * RG * (TB / TPW));
+  if (b.count == 1)
+    hipLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS, false>), g, blk, 0, s, nullptr, b.one, t, a);
+  else
+    hipLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS, true>), g, blk, 0, s, b.dd, b.one, t, a);
 }
 
-hipError_t launch_pair_band(const Dev& d, int buf, const BandArgs& a, int mixed, int dense, hipStream_t s) {
-  // bounded grids: enough work-groups to fill every CU a few times over
-  if (mixed && dense)
-    launch_pair_shape<true, 16, 8, 256>(d, buf, a, s, 1 << 16);
-  else if (mixed)
-    launch_pair_shape<true, 1, 2, 256>(d, buf, a, s, 1);
+hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense, hipStream_t s) {
+  if (b.mixed && dense)
+    launch_pair_shape<true, 16, 8, 256>(b, t, a, s, 1 << 16);
+  else if (b.mixed)
+    launch_pair_shape<true, 1, 2, 256>(b, t, a, s, 1);
   else if (dense)
-    launch_pair_shape<false, 4, 8, 256>(d, buf, a, s, 1 << 16);
+    launch_pair_shape<false, 4, 8, 256>(b, t, a, s, 1 << 16);
   else
-    launch_pair_shape<false, 2, 2, 512>(d, buf, a, s, 1);
+    launch_pair_shape<false, 2, 2, 512>(b, t, a, s, 1);
   return hipGetLastError();
 }
 
@@ -839,16 +960,28 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
 // (the sum of the bounds of its four entropies) and the bound of the row's
 // score: a test moved by at most eps changes min(0, M)^2 by at most
 // 2 |min(0, M)| eps + 3 eps^2, and not at all when M >= eps.
-__global__ __launch_bounds__(256) void k_score(double* __restrict__ M, uint8_t* __restrict__ pend,
-                                               const double* __restrict__ P, const double* __restrict__ H,
-                                               double* __restrict__ S, uint8_t* __restrict__ complete,
-                                               const int32_t* alive_list, int r, int p,
-                                               int nchunk, double n, int tb0, int ntb, int mixed,
-                                               double* __restrict__ Meps, const double* __restrict__ eH,
-                                               double* __restrict__ eT, uint8_t* __restrict__ alive,
-                                               int32_t* alive_list_w, int round_end, int t,
-                                               double gamma_mult, const int32_t* __restrict__ forced,
-                                               int forced_len, const int32_t* __restrict__ idx, Ctl* ctl) {
+__device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
+                                               double gamma_mult) {
+  const int r = rows_left(d, t), p = d.p;
+  const int nb = (r + TB - 1) / TB;
+  const int tb0 = a.tb0, ntb = min(a.ntb, nb - a.tb0);
+  if (r < 2 || ntb <= 0) return;     // the band does not exist for this data set
+  const int round_end = tb0 + ntb >= nb ? 1 : 0;  // its last band of the round
+  const int buf = t & 1;
+  double* __restrict__ M = d.M;
+  uint8_t* __restrict__ pend = d.pend;
+  const double* __restrict__ P = d.P;
+  const double* __restrict__ H = d.H;
+  double* __restrict__ S = d.S;
+  uint8_t* __restrict__ complete = d.complete;
+  const int32_t* alive_list = d.alive_list;
+  const int nchunk = d.nchunk;
+  const double n = (double)d.n;
+  const int mixed = d.mixed;
+  double* __restrict__ Meps = d.Meps;
+  const double* __restrict__ eH = d.eH;
+  double* __restrict__ eT = d.eT;
+  Ctl* ctl = d.ctl;
   __shared__ int s_stop, s_m, s_last, s_wrote;
   __shared__ double sh[4];
   __shared__ int shi[4];
@@ -926,33 +1059,48 @@ __global__ __launch_bounds__(256) void k_score(double* __restrict__ M, uint8_t* 
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  decide_group(S, alive, complete, alive_list_w, r, round_end, t, gamma_mult, forced, forced_len, idx, ctl);
+  decide_group(S, d.alive, complete, d.alive_list, r, round_end, t, gamma_mult, d.forced, d.forced_len,
+               d.idx[buf], ctl);
   if (threadIdx.x == 0) ctl->arrivals = 0;  // ready for the next launch
 }
 
-hipError_t launch_score(const Dev& d, int buf, const BandArgs& a, int round_end, int t,
-                        double gamma_mult, int dense, hipStream_t s) {
+__global__ __launch_bounds__(256) void k_score(const Dev* __restrict__ devs, const Dev one, int t, BandArgs a,
+                                               double gamma_mult) {
+  if (devs)
+    k_score_body(devs[blockIdx.z], t, a, gamma_mult);
+  else
+    k_score_body(one, t, a, gamma_mult);
+}
+
+hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_mult, int dense, hipStream_t s) {
+  const int r = b.p_max - t;
+  const int nb = (r + TB - 1) / TB;
+  if (r < 2 || a.tb0 >= nb) return hipSuccess;
   // rows when every variable is alive; after the first band of an iteration
   // few are, and a smaller grid keeps idle groups from filling the launch
-  const int rows = std::min(a.r, a.ntb * TB) + a.r;
-  hipLaunchKernelGGL(k_score, dim3(std::min(rows, dense ? 512 : 128)), dim3(256), 0, s, d.M, d.pend, d.P, d.H, d.S,
-                     d.complete, d.alive_list, a.r, d.p, a.nchunk, (double)d.n, a.tb0, a.ntb, d.mixed,
-                     d.Meps, d.eH, d.eT, d.alive, d.alive_list, round_end, t, gamma_mult, d.forced,
-                     d.forced_len, d.idx[buf], d.ctl);
+  const int rows = std::min(r, std::min(a.ntb, nb - a.tb0) * TB) + r;
+  const int cap = std::max(8, (dense ? 512 : 128) / std::min(b.count, 16));
+  hipLaunchKernelGGL(k_score, dim3(std::min(rows, cap), 1, b.count), dim3(256), 0, s, DEVS(b), t, a, gamma_mult);
   return hipGetLastError();
 }
 
 // ============================================================================
 // end of an iteration: record K, T, H; flag an iteration that is not finished
 // ============================================================================
-__global__ __launch_bounds__(256) void k_finish_iter(const int32_t* __restrict__ idx,
-                                                     const double* __restrict__ S,
-                                                     const uint8_t* __restrict__ complete,
-                                                     const double* __restrict__ H,
-                                                     const double* __restrict__ eT, int r, int p, int t,
-                                                     int32_t* order, double* Tall, uint8_t* Tstate,
-                                                     double* Hall, double* Terr, Ctl* ctl) {
-  if (halted(ctl)) return;
+__device__ __forceinline__ void k_finish_iter_body(const Dev& d, int t) {
+  const int r = rows_left(d, t), p = d.p;
+  Ctl* ctl = d.ctl;
+  if (r < 2 || halted(ctl)) return;
+  const int32_t* __restrict__ idx = d.idx[t & 1];
+  const double* __restrict__ S = d.S;
+  const uint8_t* __restrict__ complete = d.complete;
+  const double* __restrict__ H = d.H;
+  const double* __restrict__ eT = d.eT;
+  int32_t* order = d.order;
+  double* Tall = d.Tall;
+  uint8_t* Tstate = d.Tstate;
+  double* Hall = d.Hall;
+  double* Terr = d.Terr;
   if (!ctl->done) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -974,15 +1122,25 @@ __global__ __launch_bounds__(256) void k_finish_iter(const int32_t* __restrict__
   }
 }
 
-hipError_t launch_finish_iter(const Dev& d, int buf, int r, int t, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish_iter, dim3(1), dim3(256), 0, s, d.idx[buf], d.S, d.complete, d.H, d.eT, r,
-                     d.p, t, d.order, d.Tall, d.Tstate, d.Hall, d.Terr, d.ctl);
+__global__ __launch_bounds__(256) void k_finish_iter(const Dev* __restrict__ devs, const Dev one, int t) {
+  if (devs)
+    k_finish_iter_body(devs[blockIdx.z], t);
+  else
+    k_finish_iter_body(one, t);
+}
+
+hipError_t launch_finish_iter(const Batch& b, int t, hipStream_t s) {
+  if (b.p_max - t < 2) return hipSuccess;
+  hipLaunchKernelGGL(k_finish_iter, dim3(1, 1, b.count), dim3(256), 0, s, DEVS(b), t);
   return hipGetLastError();
 }
 
-__global__ void k_record_M(const double* __restrict__ M, const int32_t* __restrict__ idx, int r, int p,
-                           double* __restrict__ Mrec, const Ctl* ctl) {
-  if (halted(ctl)) return;
+__device__ __forceinline__ void k_record_M_body(const Dev& d, int t) {
+  const int r = rows_left(d, t), p = d.p;
+  if (r < 2 || t >= d.rec || halted(d.ctl)) return;
+  const double* __restrict__ M = d.M;
+  const int32_t* __restrict__ idx = d.idx[t & 1];
+  double* __restrict__ Mrec = d.Mrec + (int64_t)t * p * p;
   const int64_t total = (int64_t)r * r;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -991,21 +1149,35 @@ __global__ void k_record_M(const double* __restrict__ M, const int32_t* __restri
   }
 }
 
-hipError_t launch_record_M(const Dev& d, int buf, int r, int t, hipStream_t s) {
+__global__ void k_record_M(const Dev* __restrict__ devs, const Dev one, int t) {
+  if (devs)
+    k_record_M_body(devs[blockIdx.z], t);
+  else
+    k_record_M_body(one, t);
+}
+
+hipError_t launch_record_M(const Batch& b, int t, hipStream_t s) {
+  const int r = b.p_max - t;
+  if (r < 2) return hipSuccess;
   const int64_t total = (int64_t)r * r;
   int blocks = (int)std::min<int64_t>(1024, (total + 255) / 256);
-  hipLaunchKernelGGL(k_record_M, dim3(std::max(blocks, 1)), dim3(256), 0, s, d.M, d.idx[buf], r, d.p,
-                     d.Mrec + (int64_t)t * d.p * d.p, d.ctl);
+  hipLaunchKernelGGL(k_record_M, dim3(std::max(blocks, 1), 1, b.count), dim3(256), 0, s, DEVS(b), t);
   return hipGetLastError();
 }
 
 // ============================================================================
 // a7: UpdateData and UpdateCovMat (Sec. 3.4), compacting out the root
 // ============================================================================
-__global__ __launch_bounds__(256) void k_update_rows(const double* __restrict__ Z, double* __restrict__ Zn,
-                                                     int64_t ldz, int64_t n, const double* __restrict__ Sig,
-                                                     const double* __restrict__ dsc, int p, const Ctl* ctl) {
-  if (halted(ctl) || !ctl->done) return;
+__device__ __forceinline__ void k_update_rows_body(const Dev& d, int t) {
+  const int r = rows_left(d, t), p = d.p;
+  const Ctl* ctl = d.ctl;
+  if (r < 2 || (int)blockIdx.y >= r - 1 || halted(ctl) || !ctl->done) return;
+  const int buf = t & 1;
+  const double* __restrict__ Z = d.Z[buf];
+  double* __restrict__ Zn = d.Z[buf ^ 1];
+  const int64_t ldz = d.ldz, n = d.n;
+  const double* __restrict__ Sig = d.Sig[buf];
+  const double* __restrict__ dsc = d.dsc[buf];
   const int root = ctl->root;
   const int wn = blockIdx.y;                  // new position
   const int w = wn + (wn >= root ? 1 : 0);    // old position
@@ -1019,11 +1191,24 @@ __global__ __launch_bounds__(256) void k_update_rows(const double* __restrict__ 
     zo[k] = (dw * zw[k] - b * (dr * zr[k])) * sc;
 }
 
-__global__ __launch_bounds__(256) void k_update_sigma(const double* __restrict__ Sig, double* __restrict__ Sn,
-                                                      const double* __restrict__ dsc, double* __restrict__ dscn,
-                                                      const int32_t* __restrict__ idx, int32_t* __restrict__ idxn,
-                                                      int r, int p, int recursion, const Ctl* ctl) {
-  if (halted(ctl) || !ctl->done) return;
+__global__ __launch_bounds__(256) void k_update_rows(const Dev* __restrict__ devs, const Dev one, int t) {
+  if (devs)
+    k_update_rows_body(devs[blockIdx.z], t);
+  else
+    k_update_rows_body(one, t);
+}
+
+__device__ __forceinline__ void k_update_sigma_body(const Dev& d, int t, int recursion) {
+  const int r = rows_left(d, t), p = d.p;
+  const Ctl* ctl = d.ctl;
+  if (r < 2 || halted(ctl) || !ctl->done) return;
+  const int buf = t & 1;
+  const double* __restrict__ Sig = d.Sig[buf];
+  double* __restrict__ Sn = d.Sig[buf ^ 1];
+  const double* __restrict__ dsc = d.dsc[buf];
+  double* __restrict__ dscn = d.dsc[buf ^ 1];
+  const int32_t* __restrict__ idx = d.idx[buf];
+  int32_t* __restrict__ idxn = d.idx[buf ^ 1];
   const int root = ctl->root;
   const int rn = r - 1;
   const int64_t total = (int64_t)rn * rn;
@@ -1050,51 +1235,76 @@ __global__ __launch_bounds__(256) void k_update_sigma(const double* __restrict__
   }
 }
 
-hipError_t launch_update(const Dev& d, int buf, int r, int refresh, hipStream_t s) {
-  const int rn = r - 1;
+__global__ __launch_bounds__(256) void k_update_sigma(const Dev* __restrict__ devs, const Dev one, int t, int recursion) {
+  if (devs)
+    k_update_sigma_body(devs[blockIdx.z], t, recursion);
+  else
+    k_update_sigma_body(one, t, recursion);
+}
+
+hipError_t launch_update(const Batch& b, int t, int refresh, hipStream_t s) {
+  const int rn = b.p_max - t - 1;
   if (rn <= 0) return hipSuccess;
-  int xblocks = (int)std::min<int64_t>(64, (d.n + 255) / 256);
-  hipLaunchKernelGGL(k_update_rows, dim3(xblocks, rn), dim3(256), 0, s, d.Z[buf], d.Z[buf ^ 1], d.ldz,
-                     d.n, d.Sig[buf], d.dsc[buf], d.p, d.ctl);
+  const int xblocks = (int)std::min<int64_t>(64, (b.n_max + 255) / 256);
+  hipLaunchKernelGGL(k_update_rows, dim3(xblocks, rn, b.count), dim3(256), 0, s, DEVS(b), t);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t total = std::max<int64_t>((int64_t)rn * rn, rn);
-  int blocks = (int)std::min<int64_t>(2048, (total + 255) / 256);
-  hipLaunchKernelGGL(k_update_sigma, dim3(std::max(blocks, 1)), dim3(256), 0, s, d.Sig[buf], d.Sig[buf ^ 1],
-                     d.dsc[buf], d.dsc[buf ^ 1], d.idx[buf], d.idx[buf ^ 1], r, d.p, refresh ? 0 : 1, d.ctl);
+  int blocks = (int)std::min<int64_t>(std::max(8, 2048 / b.count), (total + 255) / 256);
+  hipLaunchKernelGGL(k_update_sigma, dim3(std::max(blocks, 1), 1, b.count), dim3(256), 0, s, DEVS(b), t,
+                     refresh ? 0 : 1);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (refresh) return launch_gram(d, buf ^ 1, rn, s);
+  if (refresh) return launch_gram(b, (t & 1) ^ 1, t + 1, s);
   return hipSuccess;
 }
 
 // Last remaining variable: appended without a comparison (Alg. 2).
-__global__ void k_last(const int32_t* idx, int p, int t, int32_t* order, double* Tall, uint8_t* Tstate,
-                       double* Terr, const Ctl* ctl) {
-  if (halted(ctl)) return;
+__device__ __forceinline__ void k_last_body(const Dev& d, int t) {
+  const int p = d.p;
+  if (rows_left(d, t) != 1 || halted(d.ctl)) return;
+  const int32_t* idx = d.idx[t & 1];
+  int32_t* order = d.order;
+  double* Tall = d.Tall;
+  uint8_t* Tstate = d.Tstate;
+  double* Terr = d.Terr;
   order[t] = idx[0];
   Tall[(int64_t)t * p + idx[0]] = 0.0;
   Tstate[(int64_t)t * p + idx[0]] = 1;
   Terr[(int64_t)t * p + idx[0]] = 0.0;
 }
 
-hipError_t launch_last(const Dev& d, int buf, int t, hipStream_t s) {
-  hipLaunchKernelGGL(k_last, dim3(1), dim3(1), 0, s, d.idx[buf], d.p, t, d.order, d.Tall, d.Tstate, d.Terr,
-                     d.ctl);
+__global__ void k_last(const Dev* __restrict__ devs, const Dev one, int t) {
+  if (devs)
+    k_last_body(devs[blockIdx.z], t);
+  else
+    k_last_body(one, t);
+}
+
+hipError_t launch_last(const Batch& b, int t, hipStream_t s) {
+  hipLaunchKernelGGL(k_last, dim3(1, 1, b.count), dim3(1), 0, s, DEVS(b), t);
   return hipGetLastError();
 }
 
 // Clear the halt raised by an unfinished iteration (not an error) so that
 // further threshold rounds can run.
-__global__ void k_resume(Ctl* ctl) {
+__device__ __forceinline__ void k_resume_body(const Dev& d) {
+  Ctl* ctl = d.ctl;
   if (ctl->status == ST_OK) {
     ctl->halt = 0;
     ctl->halt_iter = -1;
   }
 }
 
-hipError_t launch_resume(const Dev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_resume, dim3(1), dim3(1), 0, s, d.ctl);
+__global__ void k_resume(const Dev* __restrict__ devs, const Dev one) {
+  if (devs)
+    k_resume_body(devs[blockIdx.z]);
+  else
+    k_resume_body(one);
+}
+
+hipError_t launch_resume(const Batch& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_resume, dim3(1, 1, b.count), dim3(1), 0, s, DEVS(b));
   return hipGetLastError();
 }
 

@@ -7,11 +7,8 @@
 
 namespace lingam {
 
-// Variables per tile block.  A work-group evaluates one oriented tile (A, B):
-// wave w pairs row v = 8A + w with the 8 rows of block B.
+// Variables per target block of the pair kernel.
 constexpr int TB = 8;
-constexpr int PAIR_WAVES = TB;
-constexpr int PAIR_THREADS = 64 * PAIR_WAVES;
 // Row stride unit of the stored data (doubles); every sample range a kernel
 // stages starts at a multiple of it.
 constexpr int SUB = 256;
@@ -45,10 +42,17 @@ struct Ctl {
   unsigned long long bands_total;
 };
 
-// Device pointers and sizes of one search.
+// Device pointers and sizes of one search.  The kernels read it from device
+// memory: an array of them, one per data set of a batch, indexed by
+// blockIdx.z (a single search is a batch of one).
 struct Dev {
   int p = 0;                 // number of variables
   int64_t n = 0;             // samples
+  const void* X = nullptr;   // input rows on the device (read by the standardisation only)
+  int x_dtype = 0;           // 0 = double, 1 = float
+  int layout = 0;            // 0 = p x n (row = variable), 1 = n x p
+  int nchunk = 1;            // sample chunks of the pair kernel, ceil(n / chunk)
+  int limit = 0;             // iterations to run (p, or fewer when max_roots is set)
   int64_t ldz = 0;           // row stride of Z (doubles), multiple of 64
   double* Z[2] = {nullptr, nullptr};      // p x ldz normalised rows (ping-pong by iteration parity)
   // Sig holds G, the covariance of the stored rows (ld = p), and dsc the row
@@ -70,8 +74,7 @@ struct Dev {
   int32_t* alive_list = nullptr;  // [p] positions with alive = 1, ascending
   uint8_t* complete = nullptr;  // [p] every pair of the row evaluated
   uint8_t* pend = nullptr;   // p x p: partial sums written, M not yet formed
-  double* P = nullptr;       // [nchunk_max][p][p][4] per-chunk partial sums
-  int nchunk_max = 0;
+  double* P = nullptr;       // [nchunk][p][p][4] per-chunk partial sums
   Ctl* ctl = nullptr;
   int32_t* order = nullptr;  // [p]
   double* Tall = nullptr;    // [p*p]
@@ -83,36 +86,48 @@ struct Dev {
   int forced_len = 0;
   double* stats = nullptr;   // [2*p] per-row mean/variance of the input (diagnostics)
   double* Gp = nullptr;      // [gram_slices_max][p][p] per-slice partial Gram
-  int gram_slices_max = 1;
+  int gram_slices_max = 1;   // largest sample split of the Gram
 };
 
 // Parameters of one band launch of the pair kernel: every alive variable is
-// compared with the variables of target blocks [tb0, tb0 + ntb).
+// compared with the variables of target blocks [tb0, tb0 + ntb), clipped to
+// the blocks a data set has at the iteration (none: the band is skipped).
 struct BandArgs {
-  int r;          // remaining variables
-  int nb;         // blocks of TB variables, ceil(r / TB)
-  int tb0, ntb;   // target blocks of the band
-  int nchunk;     // sample chunks
+  int tb0, ntb;   // target blocks of the band (ntb large = every block from tb0 on)
   int chunk;      // samples per chunk
-  int nrg;        // row groups (set by the launcher)
+};
+
+// What a launch covers: `count` data sets whose descriptors are at `dd` on
+// the device, every one at iteration t (r = p - t variables left).  The
+// host-side maxima size the grids; each work-group reads its own sizes.
+struct Batch {
+  const Dev* dd = nullptr;   // device array [count]
+  int count = 1;
+  Dev one;                   // the descriptor itself when count == 1
+  int p_max = 0;             // largest p of the batch
+  int64_t n_max = 0;         // largest n
+  int nchunk_max = 1;
+  int gram_slices_max = 1;
+  int mixed = 0;
 };
 
 // ---- launch wrappers (kernels.hip) --------------------------------------
-hipError_t launch_standardize(const void* X, int x_dtype, int layout, int64_t n, int p,
-                              const Dev& d, hipStream_t s);
-hipError_t launch_gram(const Dev& d, int buf, int r, hipStream_t s);
-hipError_t launch_entropy(const Dev& d, int buf, int r, int mixed, hipStream_t s);
-hipError_t launch_iter_init(const Dev& d, int r, double gamma0, double adapt, hipStream_t s);
-hipError_t launch_pair_band(const Dev& d, int buf, const BandArgs& a, int mixed, int dense, hipStream_t s);
-hipError_t launch_score(const Dev& d, int buf, const BandArgs& a, int round_end, int t,
-                        double gamma_mult, int dense, hipStream_t s);
-hipError_t launch_finish_iter(const Dev& d, int buf, int r, int t, hipStream_t s);
-hipError_t launch_record_M(const Dev& d, int buf, int r, int t, hipStream_t s);
-hipError_t launch_update(const Dev& d, int buf, int r, int refresh, hipStream_t s);
-hipError_t launch_last(const Dev& d, int buf, int t, hipStream_t s);
-hipError_t launch_resume(const Dev& d, hipStream_t s);
+// t is the iteration every data set of the batch is at; buf = t & 1 selects
+// the ping-pong buffers.
+hipError_t launch_standardize(const Batch& b, hipStream_t s);
+hipError_t launch_gram(const Batch& b, int buf, int t, hipStream_t s);
+hipError_t launch_entropy(const Batch& b, int t, hipStream_t s);
+hipError_t launch_iter_init(const Batch& b, int t, double gamma0, double adapt, hipStream_t s);
+hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense, hipStream_t s);
+hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_mult, int dense, hipStream_t s);
+hipError_t launch_finish_iter(const Batch& b, int t, hipStream_t s);
+hipError_t launch_record_M(const Batch& b, int t, hipStream_t s);
+hipError_t launch_update(const Batch& b, int t, int refresh, hipStream_t s);
+hipError_t launch_last(const Batch& b, int t, hipStream_t s);
+hipError_t launch_resume(const Batch& b, hipStream_t s);
+hipError_t launch_gather(const double* X, int64_t n_src, int64_t p, const int64_t* idx, int64_t n_idx,
+                         double* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t count, uint8_t v, hipStream_t s);
-
 
 }  // namespace lingam

@@ -129,4 +129,42 @@ def test_invalid_arguments_rejected_before_device_work(lib):
 def test_batch_entry_point_reports_status(lib):
     res = (lg.LingamResult * 1)()
     st = lib.lingam_fit_order_batch(0, None, None, res)
-    assert st in (lg.E_INVALID, lg.E_UNSUPPORTED)
+    assert st == lg.E_INVALID
+
+
+def _batch_call(lib, sets_py, opts=None):
+    """Call lingam_fit_order_batch on host arrays (validation only: every call
+    here is rejected before any device work)."""
+    count = len(sets_py)
+    sets = (lg.LingamDataset * count)()
+    outs = (lg.LingamResult * count)()
+    orders = []
+    for k, (X, idx) in enumerate(sets_py):
+        sets[k].X = ctypes.c_void_p(X.ctypes.data) if X is not None else None
+        sets[k].p, sets[k].n = X.shape if X is not None else (3, 10)
+        if idx is not None:
+            sets[k].sample_idx = idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            sets[k].n_idx = idx.size
+        orders.append(np.zeros(sets[k].p, dtype=np.int32))
+        outs[k].order = orders[-1].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    o = opts if opts is not None else lg.default_opts()
+    return lib.lingam_fit_order_batch(count, sets, ctypes.byref(o), outs)
+
+
+def test_batch_validation(lib):
+    X = np.zeros((3, 10))
+    assert _batch_call(lib, [(None, None)]) == lg.E_INVALID                       # NULL X
+    assert _batch_call(lib, [(X, np.array([0, 10], dtype=np.int64))]) == lg.E_INVALID   # index >= n
+    assert _batch_call(lib, [(X, np.array([-1, 2], dtype=np.int64))]) == lg.E_INVALID   # index < 0
+    assert _batch_call(lib, [(X, np.array([1], dtype=np.int64))]) == lg.E_INVALID       # n_idx < 2
+    o = lg.default_opts()
+    o.x_dtype = 1
+    assert _batch_call(lib, [(X, np.array([0, 1, 2], dtype=np.int64))], o) == lg.E_UNSUPPORTED
+    o = lg.default_opts()
+    o.record_M_iters = 1
+    assert _batch_call(lib, [(X, None)], o) == lg.E_UNSUPPORTED
+    keep = np.array([0, 1], dtype=np.int32)
+    o = lg.default_opts()
+    o.forced_order = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    o.forced_len = 2
+    assert _batch_call(lib, [(X, None)], o) == lg.E_UNSUPPORTED

@@ -1,0 +1,99 @@
+"""Batched searches (lingam_fit_order_batch) on the GPU: every data set's
+result must be the one a separate lingam_fit_order call gives, bit for bit
+(the same kernels and per-set arithmetic run in both), including sets that
+leave the batch to finish alone, sets with an error, and bootstrap sets."""
+import numpy as np
+import pytest
+
+import paper_2109_13993_amd as lg
+from paper_2109_13993_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+def _same(b, s, tag):
+    assert b.extra["status"] == 0, tag
+    assert np.array_equal(b.order, s.order), tag
+    fin = np.isfinite(s.T)
+    assert np.array_equal(np.isfinite(b.T), fin), tag
+    assert np.array_equal(b.T[fin], s.T[fin]), tag          # bitwise
+    assert np.array_equal(b.T_state, s.T_state), tag
+    assert np.array_equal(np.isfinite(b.T_err), np.isfinite(s.T_err)), tag
+    assert np.array_equal(b.T_err[fin], s.T_err[fin]), tag
+    assert b.pairs_evaluated == s.pairs_evaluated, tag
+    assert b.threshold_rounds == s.threshold_rounds, tag
+
+
+def _mixed_batch(seed):
+    rng = np.random.default_rng(seed)
+    sets = []
+    for k, (p, n) in enumerate([(12, 1500), (40, 3000), (9, 700), (67, 5000), (25, 2048), (2, 300)]):
+        ds = synth.lingam_dataset(p, n, 0.2, "mixed", rng=np.random.default_rng(seed * 100 + k))
+        sets.append(ds.X)
+    base = synth.lingam_dataset(30, 4000, 0.15, "laplace", rng=np.random.default_rng(seed + 7)).X
+    for idx in synth.bootstrap_indices(4000, 3, rng):
+        sets.append((base, idx))
+    return sets
+
+
+def _single(item, **kw):
+    if isinstance(item, tuple):
+        base, idx = item
+        return lg.fit_order(np.ascontiguousarray(base[:, idx]), **kw)
+    return lg.fit_order(item, **kw)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_equals_single_runs(precision):
+    sets = _mixed_batch(3)
+    res = lg.fit_order_batch(sets, precision=precision)
+    assert len(res) == len(sets)
+    for k, item in enumerate(sets):
+        _same(res[k], _single(item, precision=precision), "%s set %d" % (precision, k))
+    _log("%s batch of %d: %.1f ms" % (precision, len(sets), res[0].seconds_total * 1e3))
+
+
+def test_batch_stragglers_and_options():
+    # a tiny initial threshold and multiplier need many threshold rounds, so
+    # sets halt in the batch and finish alone; max_roots and no-threshold too
+    sets = _mixed_batch(5)
+    for kw in (dict(gamma0=1e-14, gamma_mult=1.5), dict(max_roots=5), dict(use_threshold=False),
+               dict(chunk_samples=512, band_blocks=1)):
+        res = lg.fit_order_batch(sets, precision="mixed", **kw)
+        for k, item in enumerate(sets):
+            _same(res[k], _single(item, precision="mixed", **kw), "%s set %d" % (kw, k))
+        _log("%s: rounds %s" % (kw, [r.threshold_rounds for r in res]))
+
+
+def test_batch_error_in_one_set():
+    sets = _mixed_batch(9)[:4]
+    bad = sets[1].copy()
+    bad[3, 17] = np.nan
+    sets[1] = bad
+    col = sets[2].copy()
+    col[4] = 0.0                       # zero-variance row
+    sets[2] = col
+    res = lg.fit_order_batch(sets, precision="fp64")
+    assert res[1].extra["status"] == lg.E_NONFINITE and res[1].extra["bad_i"] == 3
+    assert res[2].extra["status"] == lg.E_DEGENERATE and res[2].extra["bad_i"] == 4
+    for k in (0, 3):
+        _same(res[k], _single(sets[k], precision="fp64"), "set %d" % k)
+
+
+def test_bootstrap_batch_config4_shape():
+    # 32 bootstrap resamples of one p=100, n=5000 data set (the shape of the
+    # bootstrap workload, fewer resamples), checked against single runs
+    base = synth.config_dataset(4).X
+    rng = synth.rng_for(4, 1)
+    sets = [(base, idx) for idx in synth.bootstrap_indices(base.shape[1], 32, rng)]
+    res = lg.fit_order_batch(sets, precision="mixed")
+    for k in (0, 13, 31):
+        _same(res[k], _single(sets[k], precision="mixed"), "resample %d" % k)
+    assert all(r.extra["status"] == 0 for r in res)
+    ps = sum(r.pair_samples for r in res)
+    _log("bootstrap 32 x (100 x 5000): %.1f ms, %.3e pair-samples/s" % (
+        res[0].seconds_total * 1e3, ps / res[0].seconds_total))
