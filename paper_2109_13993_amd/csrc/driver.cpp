@@ -93,19 +93,14 @@ Plan make_plan(int64_t n, const lingam_opts& o) {
   return pl;
 }
 
-// Round-0 bands of an iteration at which the largest data set has r
-// variables: consecutive groups of `band_blocks` target blocks (clipped on
-// the device to the blocks each data set has).  Later rounds use one band
-// with every block.
-std::vector<BandArgs> round0_bands(int r, const Plan& pl, bool threshold) {
-  std::vector<BandArgs> out;
+// Band slots of an iteration at which the largest data set has r variables:
+// at most the round-0 bands of band_k0 blocks each, plus QUEUED_ROUNDS - 1
+// full-band rounds.  (The device picks each slot's blocks; unused slots
+// return at once.)
+int max_slots(int r, int k0) {
   const int nb = (r + TB - 1) / TB;
-  const int K = threshold ? std::max(1, pl.band_blocks) : nb;
-  for (int tb0 = 0; tb0 < nb; tb0 += K) out.push_back(BandArgs{tb0, K, pl.chunk});
-  return out;
+  return (nb + k0 - 1) / k0 + QUEUED_ROUNDS - 1;
 }
-
-BandArgs full_band(const Plan& pl) { return BandArgs{0, 1 << 30, pl.chunk}; }
 
 lingam_status fail(lingam_status st, const std::string& msg) {
   g_last_error = msg;
@@ -253,6 +248,8 @@ Dev alloc_set(Allocs& al, int64_t n, int64_t p, const Plan& pl, const lingam_opt
   d.forced_len = o.forced_len;
   int32_t* forced_dev = al.get<int32_t>(std::max<size_t>(1, (size_t)o.forced_len));
   d.forced = forced_dev;
+  d.band_k0 = pl.band_blocks;
+  d.band_adapt = o.band_blocks > 0 ? 0 : 1;
   return d;
 }
 
@@ -289,31 +286,41 @@ struct Fit {
   std::vector<int64_t> ps;   // p of every data set
   std::vector<int> limits;   // iterations of every data set
 
-  void pair(int t, const BandArgs& a, bool dense = false) {
+  int slots = 0;             // band slots queued per iteration (0 = the most an iteration can use)
+
+  void pair(int t, const BandArgs& a, bool dense, int ntb_hint) {
     if (timer && timer->on) {
       HIPCHK(hipEventRecord(timer->next(), s));
-      HIPCHK(launch_pair_band(b, t, a, dense ? 1 : 0, s));
+      HIPCHK(launch_pair_band(b, t, a, dense ? 1 : 0, ntb_hint, s));
       HIPCHK(hipEventRecord(timer->next(), s));
       ++timer->launches;
     } else {
-      HIPCHK(launch_pair_band(b, t, a, dense ? 1 : 0, s));
+      HIPCHK(launch_pair_band(b, t, a, dense ? 1 : 0, ntb_hint, s));
     }
   }
 
-  void queue_rounds(int t, int nrounds) {
+  // one band slot: pair kernel then scores and decision
+  void slot(int t, bool first) {
     const int r = b.p_max - t;
-    for (int rd = 0; rd < nrounds; ++rd) {
-      if (rd == 0) {
-        auto bands = round0_bands(r, pl, threshold);
-        for (size_t k = 0; k < bands.size(); ++k) {
-          pair(t, bands[k], k == 0);  // the first band still has every variable alive
-          HIPCHK(launch_score(b, t, bands[k], gmult, k == 0 ? 1 : 0, s));
-        }
-      } else {
-        pair(t, full_band(pl));
-        HIPCHK(launch_score(b, t, full_band(pl), gmult, 0, s));
-      }
-    }
+    const int nb = (r + TB - 1) / TB;
+    const int hint = first ? (threshold ? std::min(pl.band_blocks, nb) : nb) : nb;
+    const BandArgs a{pl.chunk};
+    pair(t, a, first, hint);
+    HIPCHK(launch_score(b, t, a, gmult, first ? 1 : 0, hint, s));
+  }
+
+  void queue_rounds(int t) {
+    const int r = b.p_max - t;
+    int n = threshold ? max_slots(r, pl.band_blocks) : 1;
+    if (threshold && slots > 0) n = std::min(n, slots);
+    for (int k = 0; k < n; ++k) slot(t, k == 0);
+  }
+
+  // after a host sync: size the next window's band slots from the most
+  // bands one iteration of the last window needed (one spare)
+  void update_slots(int win_bands) {
+    if (win_bands > 0) slots = std::max(2, win_bands + 1);
+    HIPCHK(launch_window_reset(b, s));
   }
 
   void queue_tail(int t) {
@@ -331,8 +338,8 @@ struct Fit {
     if (any_last) HIPCHK(launch_last(b, t, s));
     if (b.p_max - t < 2) return;
     HIPCHK(launch_entropy(b, t, s));
-    HIPCHK(launch_iter_init(b, t, threshold ? gamma0 : INFINITY, GAMMA_ADAPT, s));
-    queue_rounds(t, threshold ? QUEUED_ROUNDS : 1);
+    HIPCHK(launch_iter_init(b, t, threshold ? gamma0 : INFINITY, GAMMA_ADAPT, threshold ? 1 : 0, s));
+    queue_rounds(t);
     queue_tail(t);
   }
 
@@ -342,8 +349,7 @@ struct Fit {
     HIPCHK(launch_resume(b, s));
     Ctl c{};
     for (int extra = 0;; ++extra) {
-      pair(tf, full_band(pl));
-      HIPCHK(launch_score(b, tf, full_band(pl), gmult, 0, s));
+      slot(tf, false);
       c = read_ctl(ctl_dev);
       if (c.status != ST_OK || c.done) break;
       if (extra > p - tf + 8) throw HipFail{hipErrorUnknown, "threshold rounds did not terminate", __LINE__};
@@ -368,6 +374,7 @@ struct Fit {
       for (int q = 0; q < SYNC_EVERY && t < limit; ++q, ++t) queue_iteration(t);
       c = read_ctl(ctl_dev);
       if (c.status != ST_OK) return c;
+      update_slots(c.win_bands);
       if (c.halt && c.halt_iter >= 0) {
         // iteration halt_iter needed more threshold rounds than were queued;
         // every launch queued after it returned at once, so its state is intact.
@@ -725,6 +732,9 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
       for (int q = 0; q < SYNC_EVERY && t < limit_max; ++q, ++t) f.queue_iteration(t);
       HIPCHK(hipMemcpyAsync(cs.data(), ctls, sizeof(Ctl) * count, hipMemcpyDeviceToHost, f.s));
       HIPCHK(hipStreamSynchronize(f.s));
+      int wb = 0;
+      for (const Ctl& c : cs) wb = std::max(wb, (int)c.win_bands);
+      f.update_slots(wb);
     }
     // stragglers: finish each one alone, from the iteration that halted
     for (int k = 0; k < count; ++k) {

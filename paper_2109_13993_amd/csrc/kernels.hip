@@ -451,7 +451,8 @@ hipError_t launch_entropy(const Batch& b, int t, hipStream_t s) {
 // gamma0 > 0: that initial threshold in every iteration; gamma0 <= 0: adaptive,
 // `adapt` times the previous iteration's root score (the first iteration and a
 // zero previous score use 1e-6).
-__device__ __forceinline__ void k_iter_init_body(const Dev& d, int t, double gamma0, double adapt) {
+__device__ __forceinline__ void k_iter_init_body(const Dev& d, int t, double gamma0, double adapt,
+                                                 int threshold) {
   const int r = rows_left(d, t), p = d.p;
   Ctl* ctl = d.ctl;
   if (r < 2 || halted(ctl)) return;
@@ -485,22 +486,28 @@ __device__ __forceinline__ void k_iter_init_body(const Dev& d, int t, double gam
     ctl->root = -1;
     ctl->round = 0;
     ctl->n_alive = r;
+    const int nb = (r + TB - 1) / TB;
+    ctl->tb_next = 0;
+    ctl->ntb_next = threshold ? min(d.band_k0, nb) : nb;
+    ctl->iter_bands = 0;
   }
 }
 
-__global__ void k_iter_init(const Dev* __restrict__ devs, const Dev one, int t, double gamma0, double adapt) {
+__global__ void k_iter_init(const Dev* __restrict__ devs, const Dev one, int t, double gamma0, double adapt,
+                            int threshold) {
   if (devs)
-    k_iter_init_body(devs[blockIdx.z], t, gamma0, adapt);
+    k_iter_init_body(devs[blockIdx.z], t, gamma0, adapt, threshold);
   else
-    k_iter_init_body(one, t, gamma0, adapt);
+    k_iter_init_body(one, t, gamma0, adapt, threshold);
 }
 
-hipError_t launch_iter_init(const Batch& b, int t, double gamma0, double adapt, hipStream_t s) {
+hipError_t launch_iter_init(const Batch& b, int t, double gamma0, double adapt, int threshold, hipStream_t s) {
   const int r = b.p_max - t;
   if (r < 2) return hipSuccess;
   const int64_t total = (int64_t)r * r;
   int blocks = (int)std::min<int64_t>(std::max(8, 1024 / b.count), (total + 255) / 256);
-  hipLaunchKernelGGL(k_iter_init, dim3(std::max(blocks, 1), 1, b.count), dim3(256), 0, s, DEVS(b), t, gamma0, adapt);
+  hipLaunchKernelGGL(k_iter_init, dim3(std::max(blocks, 1), 1, b.count), dim3(256), 0, s, DEVS(b), t, gamma0, adapt,
+                     threshold);
   return hipGetLastError();
 }
 
@@ -556,9 +563,7 @@ constexpr int log2_of() { return NV <= 1 ? 0 : 1 + log2_of<NV / 2>(); }
 template <bool MIXED, int RG, int TPW, int PS>
 __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a) {
   const int r = rows_left(d, t), p = d.p;
-  const int nb = (r + TB - 1) / TB;
-  a.ntb = min(a.ntb, nb - a.tb0);   // the band's blocks that exist for this data set
-  if (r < 2 || a.ntb <= 0) return;
+  if (r < 2) return;
   const int buf = t & 1;
   const double* __restrict__ Z = d.Z[buf];
   const int64_t ldz = d.ldz, n = d.n;
@@ -581,23 +586,26 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
   __shared__ double lds[2][TB][PS];  // the 8 rows of target block B, two stages
   __shared__ double s_sc[NW][TPW];   // per-pair scale s = 1/sqrt(1 - b^2)
   __shared__ uint32_t s_mask[NW];
-  __shared__ int s_stop, s_m;
-  // the stop decision and the alive count are read once and shared, so the
-  // whole work-group decides together
+  __shared__ int s_stop, s_m, s_tb0, s_ntb;
+  // the stop decision, the alive count and the band are read once and
+  // shared, so the whole work-group decides together
   if (threadIdx.x == 0) {
     s_stop = halted(ctl) || ctl->done;
     s_m = ctl->n_alive;
+    s_tb0 = ctl->tb_next;
+    s_ntb = ctl->ntb_next;
   }
   __syncthreads();
   const int m = s_m;
   if (s_stop) return;
+  const int tb0 = s_tb0, ntb = s_ntb;
   // items (row group, target block, chunk) that exist for this alive count;
   // the grid is bounded and each work-group walks its share of them.  Work-
   // groups are dealt round-robin over the 8 XCDs, so each XCD takes one
   // contiguous eighth of the items (same chunk and target block, different
   // row groups) and its work-groups share the XCD's L2.
   const int nrg = (m + RG - 1) / RG;
-  const int items = nrg * a.ntb * nchunk;
+  const int items = nrg * ntb * nchunk;
   const int xcd = blockIdx.x % 8, per_xcd = gridDim.x / 8;
   const int ipx = (items + 7) / 8;
   const int lo = xcd * ipx, hi = min(items, lo + ipx);
@@ -605,9 +613,9 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
   const int lane = threadIdx.x % 64;
   for (int item = lo + (int)(blockIdx.x / 8); item < hi; item += per_xcd) {
   const int g = item % nrg;
-  const int tb = (item / nrg) % a.ntb;
-  const int chunk = item / (nrg * a.ntb);
-  const int B = a.tb0 + tb;
+  const int tb = (item / nrg) % ntb;
+  const int chunk = item / (nrg * ntb);
+  const int B = tb0 + tb;
   const int q = g * RG + wave / WPR;
   const int j0 = (wave % WPR) * TPW;  // first target of this wave within B
   const int v = q < m ? alive_list[q] : -1;
@@ -615,7 +623,7 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
   uint32_t mask = 0;
   if (v >= 0) {
     const int bv = v / TB;
-    const bool v_in_targets = bv >= a.tb0 && bv < a.tb0 + a.ntb;
+    const bool v_in_targets = bv >= tb0 && bv < tb0 + ntb;
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int w = B * TB + j0 + j;
@@ -823,11 +831,12 @@ static int resident_groups() {
 }
 
 template <bool MIXED, int RG, int TPW, int PS>
-static void launch_pair_shape(const Batch& b, int t, const BandArgs& a, hipStream_t s, int max_waves) {
+static void launch_pair_shape(const Batch& b, int t, const BandArgs& a, int ntb_hint, hipStream_t s,
+                              int max_waves) {
   const int r = b.p_max - t;
   const int nb = (r + TB - 1) / TB;
-  const int ntb = std::min(a.ntb, nb - a.tb0);
-  if (r < 2 || ntb <= 0) return;
+  const int ntb = std::max(1, std::min(ntb_hint, nb));  // most target blocks the band can have
+  if (r < 2) return;
   const int nrg = (r + RG - 1) / RG;
   // at most max_waves generations of resident work-groups over the batch;
   // sparse bands use one, so no work-group waits for a slot only to find
@@ -842,15 +851,15 @@ static void launch_pair_shape(const Batch& b, int t, const BandArgs& a, hipStrea
     hipLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS, true>), g, blk, 0, s, b.dd, b.one, t, a);
 }
 
-hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense, hipStream_t s) {
+hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense, int ntb_hint, hipStream_t s) {
   if (b.mixed && dense)
-    launch_pair_shape<true, 16, 8, 256>(b, t, a, s, 1 << 16);
+    launch_pair_shape<true, 16, 8, 256>(b, t, a, ntb_hint, s, 1 << 16);
   else if (b.mixed)
-    launch_pair_shape<true, 1, 2, 256>(b, t, a, s, 1);
+    launch_pair_shape<true, 1, 2, 256>(b, t, a, ntb_hint, s, 1);
   else if (dense)
-    launch_pair_shape<false, 4, 8, 256>(b, t, a, s, 1 << 16);
+    launch_pair_shape<false, 4, 8, 256>(b, t, a, ntb_hint, s, 1 << 16);
   else
-    launch_pair_shape<false, 2, 2, 512>(b, t, a, s, 1);
+    launch_pair_shape<false, 2, 2, 512>(b, t, a, ntb_hint, s, 1);
   return hipGetLastError();
 }
 
@@ -948,6 +957,7 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
       ctl->round += 1;
     }
     ctl->bands_total += 1;
+    ctl->iter_bands += 1;
   }
 }
 
@@ -963,10 +973,8 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
 __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
                                                double gamma_mult) {
   const int r = rows_left(d, t), p = d.p;
+  if (r < 2) return;
   const int nb = (r + TB - 1) / TB;
-  const int tb0 = a.tb0, ntb = min(a.ntb, nb - a.tb0);
-  if (r < 2 || ntb <= 0) return;     // the band does not exist for this data set
-  const int round_end = tb0 + ntb >= nb ? 1 : 0;  // its last band of the round
   const int buf = t & 1;
   double* __restrict__ M = d.M;
   uint8_t* __restrict__ pend = d.pend;
@@ -982,16 +990,20 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
   const double* __restrict__ eH = d.eH;
   double* __restrict__ eT = d.eT;
   Ctl* ctl = d.ctl;
-  __shared__ int s_stop, s_m, s_last, s_wrote;
+  __shared__ int s_stop, s_m, s_last, s_wrote, s_tb0, s_ntb;
   __shared__ double sh[4];
   __shared__ int shi[4];
   if (threadIdx.x == 0) {
     s_stop = halted(ctl) || ctl->done;
     s_m = ctl->n_alive;
     s_wrote = 0;
+    s_tb0 = ctl->tb_next;
+    s_ntb = ctl->ntb_next;
   }
   __syncthreads();
   if (s_stop) return;
+  const int tb0 = s_tb0, ntb = s_ntb;
+  const int round_end = tb0 + ntb >= nb ? 1 : 0;  // the last band of the round
   const int m = s_m;
   const int t_lo = tb0 * TB, t_hi = min(r, (tb0 + ntb) * TB);
   const int rows = (t_hi - t_lo) + m;
@@ -1061,6 +1073,24 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
   __threadfence();
   decide_group(S, d.alive, complete, d.alive_list, r, round_end, t, gamma_mult, d.forced, d.forced_len,
                d.idx[buf], ctl);
+  if (threadIdx.x == 0 && !ctl->done && ctl->status == ST_OK) {
+    // the next band: after the end of a round every block at once; within
+    // round 0 the following blocks, as many as bring the band near the
+    // target work for the rows still below the threshold
+    if (round_end) {
+      ctl->tb_next = 0;
+      ctl->ntb_next = nb;
+    } else {
+      const int left = nb - (tb0 + ntb);
+      int k = d.band_k0;
+      if (d.band_adapt) {
+        const double want = BAND_TARGET_PAIR_SAMPLES / ((double)TB * (double)max(ctl->n_alive, 1) * n);
+        k = want >= (double)left ? left : max(k, (int)ceil(want));
+      }
+      ctl->tb_next = tb0 + ntb;
+      ctl->ntb_next = min(k, left);
+    }
+  }
   if (threadIdx.x == 0) ctl->arrivals = 0;  // ready for the next launch
 }
 
@@ -1072,15 +1102,27 @@ __global__ __launch_bounds__(256) void k_score(const Dev* __restrict__ devs, con
     k_score_body(one, t, a, gamma_mult);
 }
 
-hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_mult, int dense, hipStream_t s) {
+hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_mult, int dense, int ntb_hint,
+                        hipStream_t s) {
   const int r = b.p_max - t;
+  if (r < 2) return hipSuccess;
   const int nb = (r + TB - 1) / TB;
-  if (r < 2 || a.tb0 >= nb) return hipSuccess;
   // rows when every variable is alive; after the first band of an iteration
   // few are, and a smaller grid keeps idle groups from filling the launch
-  const int rows = std::min(r, std::min(a.ntb, nb - a.tb0) * TB) + r;
+  const int rows = std::min(r, std::max(1, std::min(ntb_hint, nb)) * TB) + r;
   const int cap = std::max(8, (dense ? 512 : 128) / std::min(b.count, 16));
   hipLaunchKernelGGL(k_score, dim3(std::min(rows, cap), 1, b.count), dim3(256), 0, s, DEVS(b), t, a, gamma_mult);
+  return hipGetLastError();
+}
+
+__global__ void k_window_reset(const Dev* __restrict__ devs, const Dev one) {
+  Ctl* ctl = devs ? devs[blockIdx.z].ctl : one.ctl;
+  ctl->win_bands = 0;
+}
+
+// Clear the per-window band maximum of every data set (read by the host).
+hipError_t launch_window_reset(const Batch& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_window_reset, dim3(1, 1, b.count), dim3(1), 0, s, DEVS(b));
   return hipGetLastError();
 }
 
@@ -1119,6 +1161,7 @@ __device__ __forceinline__ void k_finish_iter_body(const Dev& d, int t) {
   if (threadIdx.x == 0) {
     order[t] = idx[ctl->root];
     ctl->rounds_total += (unsigned long long)(ctl->round + 1);
+    ctl->win_bands = max(ctl->win_bands, ctl->iter_bands);
   }
 }
 

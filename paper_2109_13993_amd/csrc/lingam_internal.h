@@ -35,6 +35,10 @@ struct Ctl {
   int32_t round;        // threshold round of the current iteration
   uint32_t arrivals;     // work-groups of the running score launch that have finished
   int32_t n_alive;        // entries of the alive list (variables with S <= gamma)
+  int32_t tb_next;        // target blocks [tb_next, tb_next + ntb_next) of the next band
+  int32_t ntb_next;
+  int32_t iter_bands;     // bands run in the current iteration
+  int32_t win_bands;      // most bands of one iteration since the host last looked
   double last_root_S;     // score of the previous iteration's root (adaptive gamma0)
   unsigned long long pairs_evaluated;
   unsigned long long pairs_computed;
@@ -53,6 +57,8 @@ struct Dev {
   int layout = 0;            // 0 = p x n (row = variable), 1 = n x p
   int nchunk = 1;            // sample chunks of the pair kernel, ceil(n / chunk)
   int limit = 0;             // iterations to run (p, or fewer when max_roots is set)
+  int band_k0 = 4;           // target blocks of an iteration's first band (every block: no threshold)
+  int band_adapt = 1;        // 1 = size later bands from the alive count, 0 = band_k0 blocks each
   int64_t ldz = 0;           // row stride of Z (doubles), multiple of 64
   double* Z[2] = {nullptr, nullptr};      // p x ldz normalised rows (ping-pong by iteration parity)
   // Sig holds G, the covariance of the stored rows (ld = p), and dsc the row
@@ -89,11 +95,16 @@ struct Dev {
   int gram_slices_max = 1;   // largest sample split of the Gram
 };
 
-// Parameters of one band launch of the pair kernel: every alive variable is
-// compared with the variables of target blocks [tb0, tb0 + ntb), clipped to
-// the blocks a data set has at the iteration (none: the band is skipped).
+// Samples per pair-kernel band that later bands of round 0 aim at: their
+// target-block count is chosen so that (alive rows) x (targets) x n is
+// about this, between band_k0 and the blocks left.
+constexpr double BAND_TARGET_PAIR_SAMPLES = 8e7;
+
+// Parameters of one band launch of the pair kernel.  Which target blocks
+// the band covers is decided on the device (Ctl::tb_next, ntb_next), so
+// the host only queues band slots; a slot after the iteration is decided
+// returns at once.
 struct BandArgs {
-  int tb0, ntb;   // target blocks of the band (ntb large = every block from tb0 on)
   int chunk;      // samples per chunk
 };
 
@@ -117,9 +128,11 @@ struct Batch {
 hipError_t launch_standardize(const Batch& b, hipStream_t s);
 hipError_t launch_gram(const Batch& b, int buf, int t, hipStream_t s);
 hipError_t launch_entropy(const Batch& b, int t, hipStream_t s);
-hipError_t launch_iter_init(const Batch& b, int t, double gamma0, double adapt, hipStream_t s);
-hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense, hipStream_t s);
-hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_mult, int dense, hipStream_t s);
+hipError_t launch_iter_init(const Batch& b, int t, double gamma0, double adapt, int threshold, hipStream_t s);
+hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense, int ntb_hint, hipStream_t s);
+hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_mult, int dense, int ntb_hint,
+                        hipStream_t s);
+hipError_t launch_window_reset(const Batch& b, hipStream_t s);
 hipError_t launch_finish_iter(const Batch& b, int t, hipStream_t s);
 hipError_t launch_record_M(const Batch& b, int t, hipStream_t s);
 hipError_t launch_update(const Batch& b, int t, int refresh, hipStream_t s);
