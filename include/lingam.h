@@ -80,9 +80,11 @@ typedef struct lingam_opts {
                                   forced_len iterations (scores are still computed) */
   int32_t forced_len;
   int32_t record_M_iters;      /* record the full test matrix for the first k iterations */
-  int32_t band_blocks;         /* tuning: target blocks of 8 variables per threshold band
-                                  (every variable below the threshold is compared with these
-                                  targets before the threshold state is refreshed); 0 = 4 */
+  int32_t band_blocks;         /* tuning: the threshold rounds compare every variable still below
+                                  the threshold with bands of target blocks (8 variables each),
+                                  refreshing the threshold state after each band.  0 (default): a
+                                  first band of 1 block, then bands sized from the number of
+                                  variables still below the threshold; k > 0: k blocks per band */
   int32_t chunk_samples;       /* tuning: samples per work-group chunk (multiple of 256), 0 = auto */
   void* stream;                /* hipStream_t to run on; NULL = a library-owned stream */
   int32_t profile;             /* 1 = time every pair-kernel launch with HIP events on the

@@ -72,7 +72,7 @@ struct OwnedStream {
 constexpr int SYNC_EVERY = 16;   // iterations queued between host checks
 constexpr int QUEUED_ROUNDS = 4; // threshold rounds queued per iteration
 constexpr int GRAM_SLICES_MAX = 16;  // sample slices of the split Gram
-constexpr int BAND_BLOCKS_DEFAULT = 4;  // target blocks per threshold band
+constexpr int BAND_BLOCKS_DEFAULT = 1;  // target blocks of the first threshold band
 constexpr double GAMMA_ADAPT = 2.0;  // adaptive gamma0 = this x previous root score
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }

@@ -805,13 +805,15 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(const Dev* _
     k_pair_band_body<MIXED, RG, TPW, PS>(one, t, a);
 }
 
-// Work-group shapes of the pair kernel (results do not depend on them).
-// Dense bands (every variable still alive): 16 rows x 8 targets per wave,
-// so each staged target block is shared by 16 rows.  Sparse bands: one row
-// per group, its 8 targets split over 4 waves of 2, so the few alive rows
-// spread over many small groups that the CUs hold four at a time.  The FP64
-// variant uses fewer waves per group because its terms need more registers
-// per lane.
+// Work-group shapes of the pair kernel (results do not depend on them;
+// chosen by measurement on MI355X).  Mixed mode: 2 rows per group, each
+// row's 8 targets split over 2 waves of 4, 256-sample stages -- small groups
+// that the CUs hold several at a time, so the first band of an iteration
+// (every row, one target block) and the later bands (few rows, several
+// blocks) both spread over the whole device.  The first band's grid may
+// take many generations of groups; later bands are bounded to one.  The
+// FP64 variant uses more rows per group because its terms need more
+// registers per lane.
 template <bool MIXED, int RG, int TPW, int PS>
 static int resident_groups() {
   static std::atomic<int> cached{0};
@@ -853,9 +855,9 @@ static void launch_pair_shape(const Batch& b, int t, const BandArgs& a, int ntb_
 
 hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense, int ntb_hint, hipStream_t s) {
   if (b.mixed && dense)
-    launch_pair_shape<true, 16, 8, 256>(b, t, a, ntb_hint, s, 1 << 16);
+    launch_pair_shape<true, 2, 4, 256>(b, t, a, ntb_hint, s, 1 << 16);
   else if (b.mixed)
-    launch_pair_shape<true, 1, 2, 256>(b, t, a, ntb_hint, s, 1);
+    launch_pair_shape<true, 2, 4, 256>(b, t, a, ntb_hint, s, 1);
   else if (dense)
     launch_pair_shape<false, 4, 8, 256>(b, t, a, ntb_hint, s, 1 << 16);
   else

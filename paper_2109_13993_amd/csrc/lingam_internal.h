@@ -98,7 +98,7 @@ struct Dev {
 // Samples per pair-kernel band that later bands of round 0 aim at: their
 // target-block count is chosen so that (alive rows) x (targets) x n is
 // about this, between band_k0 and the blocks left.
-constexpr double BAND_TARGET_PAIR_SAMPLES = 8e7;
+constexpr double BAND_TARGET_PAIR_SAMPLES = 4e7;
 
 // Parameters of one band launch of the pair kernel.  Which target blocks
 // the band covers is decided on the device (Ctl::tb_next, ntb_next), so
