@@ -74,6 +74,10 @@ constexpr int QUEUED_ROUNDS = 4; // threshold rounds queued per iteration
 constexpr int GRAM_SLICES_MAX = 16;  // sample slices of the split Gram
 constexpr int BAND_BLOCKS_DEFAULT = 1;  // target blocks of the first threshold band
 constexpr double GAMMA_ADAPT = 2.0;  // adaptive gamma0 = this x previous root score
+// Default Gram refresh period of the mixed mode: between refreshes the
+// paper's rank-1 UpdateCovMat carries the covariance; its drift over a few
+// iterations stays far below the binary32 rounding of the per-sample terms.
+constexpr int REFRESH_MIXED = 8;
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -287,6 +291,7 @@ struct Fit {
   std::vector<int> limits;   // iterations of every data set
 
   int slots = 0;             // band slots queued per iteration (0 = the most an iteration can use)
+  int refresh_every = 1;     // Gram refresh period (0 = the rank-1 recursion only)
 
   void pair(int t, const BandArgs& a, bool dense, int ntb_hint) {
     if (timer && timer->on) {
@@ -326,7 +331,7 @@ struct Fit {
   void queue_tail(int t) {
     HIPCHK(launch_finish_iter(b, t, s));
     if (t < rec) HIPCHK(launch_record_M(b, t, s));
-    const bool refresh = o.cov_refresh_every > 0 && ((t + 1) % o.cov_refresh_every == 0);
+    const bool refresh = refresh_every > 0 && ((t + 1) % refresh_every == 0);
     HIPCHK(launch_update(b, t, refresh ? 1 : 0, s));
   }
 
@@ -446,7 +451,7 @@ void lingam_opts_default(lingam_opts* o) {
   o->use_threshold = 1;
   o->gamma0 = 0.0;
   o->gamma_mult = 4.0;
-  o->cov_refresh_every = 1;
+  o->cov_refresh_every = -1;
   o->max_roots = 0;
   o->forced_order = nullptr;
   o->forced_len = 0;
@@ -522,6 +527,8 @@ lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam
     timer.on = o.profile != 0;
     f.o = o;
     f.s = os.s;
+    f.refresh_every = o.cov_refresh_every >= 0 ? o.cov_refresh_every
+                      : (o.precision == LINGAM_PREC_MIXED ? REFRESH_MIXED : 1);
     const bool mixed = o.precision == LINGAM_PREC_MIXED;
     f.threshold = o.use_threshold != 0;
     f.gamma0 = o.gamma0 > 0 ? o.gamma0 : 0.0;  // 0 = adaptive
@@ -639,6 +646,8 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
     timer.on = o.profile != 0;
     f.o = o;
     f.s = os.s;
+    f.refresh_every = o.cov_refresh_every >= 0 ? o.cov_refresh_every
+                      : (o.precision == LINGAM_PREC_MIXED ? REFRESH_MIXED : 1);
     const bool mixed = o.precision == LINGAM_PREC_MIXED;
     f.threshold = o.use_threshold != 0;
     f.gamma0 = o.gamma0 > 0 ? o.gamma0 : 0.0;

@@ -886,8 +886,11 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
   const int want = t < forced_len ? forced[t] : -1;
   double minc = INFINITY, mini = INFINITY;
   int ci = 0x7fffffff, pos = -1, has = 0;  // has: bit 0 some complete row, bit 1 some incomplete row
-  for (int y = tid; y < r; y += 256) {
-    const double sy = S[y];
+  // the scores of the first KC * 256 positions stay in registers for the
+  // compaction below
+  constexpr int KC = 8;
+  double sv[KC];
+  auto visit = [&](int y, double sy) {
     if (complete[y]) {
       has |= 1;
       if (sy < minc || (sy == minc && y < ci)) { minc = sy; ci = y; }
@@ -896,7 +899,18 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
       mini = fmin(mini, sy);
     }
     if (want >= 0 && idx[y] == want) pos = y;
+  };
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int y = tid + 256 * k;
+    sv[k] = y < r ? S[y] : INFINITY;
   }
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int y = tid + 256 * k;
+    if (y < r) visit(y, sv[k]);
+  }
+  for (int y = tid + 256 * KC; y < r; y += 256) visit(y, S[y]);
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     const double oc = __shfl_xor(minc, off, 64);
@@ -930,9 +944,8 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
   // threshold state for the next band and the compacted alive list, in
   // ascending position
   int base = 0;
-  for (int y0 = 0; y0 < r; y0 += 256) {
-    const int y = y0 + tid;
-    const int a = y < r && S[y] <= gamma ? 1 : 0;
+  auto compact = [&](int y, double sy) {
+    const int a = y < r && sy <= gamma ? 1 : 0;
     if (y < r) alive[y] = (uint8_t)a;
     const unsigned long long bal = __ballot(a);
     if (lane == 0) sh_cnt[wv] = __popcll(bal);
@@ -943,7 +956,11 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
     if (a) alive_list[before] = y;
     base += (sh_cnt[0] + sh_cnt[1]) + (sh_cnt[2] + sh_cnt[3]);
     __syncthreads();
-  }
+  };
+#pragma unroll
+  for (int k = 0; k < KC; ++k)
+    if (256 * k < r) compact(tid + 256 * k, sv[k]);
+  for (int y0 = 256 * KC; y0 < r; y0 += 256) compact(y0 + tid, y0 + tid < r ? S[y0 + tid] : INFINITY);
   if (tid == 0) {
     ctl->gamma = gamma;
     ctl->n_alive = base;

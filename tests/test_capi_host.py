@@ -84,7 +84,7 @@ def test_struct_layout_matches_header():
 def test_defaults_and_status_strings(lib):
     o = lg.default_opts()
     assert o.struct_size == ctypes.sizeof(lg.LingamOpts)
-    assert o.use_threshold == 1 and o.precision == 0 and o.cov_refresh_every == 1
+    assert o.use_threshold == 1 and o.precision == 0 and o.cov_refresh_every == -1
     assert o.gamma0 == 0.0 and o.gamma_mult == 4.0
     for s in range(7):
         assert len(lg.status_string(s)) > 0

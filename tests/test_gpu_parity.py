@@ -125,9 +125,14 @@ def test_threshold_keeps_order_and_complete_scores():
                 assert on.pairs_evaluated < off.pairs_evaluated
 
 
-def test_config2_fp64_parity():
+@pytest.fixture(scope="module")
+def cfg2():
     ds = synth.config_dataset(2)   # p=100, n=10000
-    o = oracle.fit_order(ds.X, M_iters=100)
+    return ds, oracle.fit_order(ds.X, M_iters=100)
+
+
+def test_config2_fp64_parity(cfg2):
+    ds, o = cfg2
     g = lg.fit_order(ds.X, precision="fp64", use_threshold=False, record_M_iters=100)
     assert list(g.order) == list(o["order"])
     assert g.pairs_evaluated == 101 * 100 * 99 // 6
@@ -137,6 +142,20 @@ def test_config2_fp64_parity():
     small = lg.fit_order(ds.X, precision="fp64", band_blocks=1)
     assert list(small.order) == list(o["order"])
     assert small.pairs_evaluated < g.pairs_evaluated
+
+
+@pytest.mark.parametrize("every", [4, 0])
+def test_refresh_period_fp64(cfg2, every):
+    # Gram refresh every 4 iterations, or only the rank-1 UpdateCovMat
+    # recursion: the recursion drifts from the data, so only the order and a
+    # loose score agreement are expected
+    ds, o = cfg2
+    g = lg.fit_order(ds.X, precision="fp64", cov_refresh_every=every)
+    assert list(g.order) == list(o["order"])
+    both = (g.T_state == 1) & np.isfinite(o["T"])
+    rel = np.abs(g.T[both] - o["T"][both]) / np.maximum(np.abs(o["T"][both]), 1e-12)
+    _log("refresh every %d: max rel |dT| %.3e" % (every, rel.max()))
+    assert rel.max() < 1e-4
 
 
 # ---- full size (p=500, n=20000): sampled outputs --------------------------------
