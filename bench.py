@@ -100,6 +100,48 @@ def mixed_error_report(rm, r64, p):
             "gap_rule_certified_iterations": certified, "gap_rule_violations": violations}
 
 
+def batch_report(lg, synth, sequential_sample=8):
+    """Batched searches (lingam_fit_order_batch), mixed precision: 256
+    bootstrap resamples of one p=100, n=5000 data set, and 64 data sets of
+    uneven shape (p in [20, 200], n in [1000, 20000]).  Makespan, aggregate
+    evaluated pair-samples/s, and the same sets run one lingam_fit_order call
+    at a time (a sample of them, scaled by exact pair-sample counts)."""
+    import numpy as np
+    import torch
+    out = {}
+    base = synth.config_dataset(4).X
+    boot = [(base, idx) for idx in synth.bootstrap_indices(base.shape[1], 256, synth.rng_for(4, 1))]
+    uneven = [d.X for d in synth.uneven_datasets(64, synth.rng_for(4, 2))]
+    for name, sets in (("bootstrap_256_p100_n5000", boot), ("uneven_64_p20-200_n1000-20000", uneven)):
+        lg.fit_order_batch(sets[:8], precision="mixed", want_T=False)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = lg.fit_order_batch(sets, precision="mixed", want_T=False)
+        dt = time.perf_counter() - t0
+        ps = sum(r.pair_samples for r in res)
+        ok = all(r.extra["status"] == 0 for r in res)
+        # one call per data set, on an evenly spaced sample of the sets
+        pick = np.linspace(0, len(sets) - 1, sequential_sample).astype(int)
+        t0 = time.perf_counter()
+        ps_seq = 0
+        same = True
+        for k in pick:
+            item = sets[k]
+            X = np.ascontiguousarray(item[0][:, item[1]]) if isinstance(item, tuple) else item
+            r1 = lg.fit_order(X, precision="mixed", want_T=False, want_H=False)
+            ps_seq += r1.pair_samples
+            same &= bool(np.array_equal(r1.order, res[k].order))
+        dt_seq = time.perf_counter() - t0
+        seq_rate = ps_seq / dt_seq
+        out[name] = {"sets": len(sets), "makespan_ms": dt * 1e3, "pair_samples_per_s": ps / dt,
+                     "all_ok": ok, "one_call_per_set_pair_samples_per_s": seq_rate,
+                     "speedup_vs_one_call_per_set": (ps / dt) / seq_rate,
+                     "orders_equal_single_calls": same}
+        log("batch %s: %d sets in %.1f ms, %.3e pair-samples/s (one call per set: %.3e/s, x%.1f)" % (
+            name, len(sets), dt * 1e3, ps / dt, seq_rate, (ps / dt) / seq_rate))
+    return out
+
+
 def cpu_baseline(X, nvars):
     import oracle
     p, n = X.shape
@@ -123,6 +165,7 @@ def main():
     ap.add_argument("--cpu-vars", type=int, default=160, help="variables in the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-search workloads")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -206,6 +249,8 @@ def main():
         out["order_first_difference"] = first_diff
         log("fp64: %.1f ms/search, %.3e pair-samples/s, pair kernel %.1f ms; orders equal: %s" % (
             t64 * 1e3, v64, k64 * 1e3, same))
+    if not args.no_batch:
+        out["batch"] = batch_report(lg, synth)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(ds.X, args.cpu_vars)
         log("cpu oracle: %.3e pair-samples/s on %d threads" % (

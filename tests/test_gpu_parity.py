@@ -203,6 +203,40 @@ def test_fullsize_sampled_fp64_teacher_forced(cfg3):
     _sampled_check(X, g, prefix, t, rest, np.random.default_rng(1), 4, 24, "cfg3 forced")
 
 
+def test_largest_config_first_roots():
+    # p=1000, n=50000 (uniform noise): the first 5 roots of the FP64 search.
+    # The oracle cannot run this search whole; at each of the 5 iterations it
+    # scores (with the GPU's root prefix) the GPU root and 5 other sampled
+    # variables: the scores must agree and the root's must be the largest.
+    ds = synth.config_dataset(5)
+    X = ds.X
+    p = X.shape[0]
+    g = lg.fit_order(X, precision="fp64", max_roots=5)
+    rng = np.random.default_rng(5)
+    for t in range(5):
+        prefix = [int(v) for v in g.order[:t]]
+        root = int(g.order[t])
+        rest = sorted(set(range(p)) - set(prefix) - {root})
+        vars_ = sorted([root] + rng.choice(rest, 5, replace=False).tolist())
+        T, _ = oracle.sampled_at(X, prefix, t, vars=vars_, pairs=[])
+        T = np.asarray(T)
+        got = g.T[t, vars_]
+        fin = g.T_state[t, vars_] == 1
+        rel = np.abs(got[fin] - T[fin]) / np.maximum(np.abs(T[fin]), 1e-12)
+        _log("p=1000 t=%d root %d: T %.6e, sampled max %.6e, max rel |dT| %.2e" % (
+            t, root, T[vars_.index(root)], np.max(np.delete(T, vars_.index(root))),
+            rel.max() if rel.size else 0.0))
+        assert fin[vars_.index(root)]
+        assert rel.size == 0 or rel.max() < 1e-8
+        # the oracle's full score of the root is the largest (up to the FP64 tolerance)
+        others = np.delete(T, vars_.index(root))
+        assert np.all(T[vars_.index(root)] >= others - 1e-8 * np.abs(others) - 1e-15)
+    # the whole mixed-precision search at this size
+    gm = lg.fit_order(X, precision="mixed")
+    assert list(gm.order[:5]) == list(g.order[:5])
+    _log("p=1000 n=50000 mixed: full order in %.2f s, %d pairs evaluated" % (gm.seconds_total, gm.pairs_evaluated))
+
+
 def test_fullsize_runs_are_deterministic_and_threshold_exact(cfg3):
     X = cfg3.X
     a = lg.fit_order(X, precision="mixed")
