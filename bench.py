@@ -207,6 +207,12 @@ def main():
             t_mix * 1e3, value, kern_s * 1e3, launches, kern_s / max(launches, 1) * 1e6,
             res_mix[-1].pairs_evaluated, res_mix[-1].pairs_computed))
 
+    # the same search with X in host memory (the copy to the device inside the call)
+    t0 = time.perf_counter()
+    rh = lg.fit_order(ds.X, precision="mixed")
+    t_host = time.perf_counter() - t0
+    log("mixed, host input: %.1f ms/search" % (t_host * 1e3))
+
     out = {
         "metric": "pair-sample evals/s + causal-order wall time, p=500 n=20k, FP32 vs FP64",
         "value": value,
@@ -233,6 +239,7 @@ def main():
         "pairs_computed": res_mix[-1].pairs_computed,
         "effective_pair_samples_per_s": (p + 1) * p * (p - 1) // 6 * n / t_mix,
         "threshold_rounds": res_mix[-1].threshold_rounds,
+        "host_input": {"ms_per_step": t_host * 1e3, "pair_samples_per_s": rh.pair_samples / t_host},
     }
     if not args.no_fp64:
         steps64 = args.fp64_steps if args.fp64_steps is not None else min(args.steps, 3)
