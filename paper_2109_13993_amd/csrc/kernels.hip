@@ -1040,8 +1040,12 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
   const double hx = H[x];
   for (int w = threadIdx.x; w < r; w += 256) {
     if (w == x) continue;
-    double mv, ev = 0.0;
-    if (pend[(int64_t)x * p + w]) {
+    // the flag, the stored test and its bound are fetched together; only a
+    // pending test needs a second, dependent fetch (its chunk partials)
+    const int64_t o = (int64_t)x * p + w;
+    const uint8_t pd = pend[o];
+    double mv = M[o], ev = mixed ? Meps[o] : 0.0;
+    if (pd) {
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       for (int c = 0; c < nchunk; ++c) {
         const double* q = P + (((int64_t)c * p + x) * p + w) * 4;
@@ -1050,15 +1054,14 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
       const double h_rx = happ_from_sums(a0, a1, n);  // H(r_x^(w))
       const double h_rw = happ_from_sums(a2, a3, n);  // H(r_w^(x))
       mv = (H[w] + h_rx) - (hx + h_rw);               // Eq. (Itest)
-      M[(int64_t)x * p + w] = mv;
-      pend[(int64_t)x * p + w] = 0;
+      M[o] = mv;
+      pend[o] = 0;
       if (mixed) {
         ev = (eH[x] + eH[w]) + (happ_err_mixed(a0, a1, n) + happ_err_mixed(a2, a3, n));
-        Meps[(int64_t)x * p + w] = ev;
+        Meps[o] = ev;
       }
-    } else {
-      mv = M[(int64_t)x * p + w];
-      if (mixed && !__builtin_isnan(mv)) ev = Meps[(int64_t)x * p + w];
+    } else if (__builtin_isnan(mv)) {
+      ev = 0.0;   // not evaluated (its bound slot holds an earlier iteration's value)
     }
     if (__builtin_isnan(mv)) {
       incomplete = 1;
