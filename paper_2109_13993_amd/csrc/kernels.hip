@@ -395,7 +395,31 @@ hipError_t launch_gram(const Batch& b, int buf, int t, hipStream_t s) {
 // ============================================================================
 // a3: per-variable entropy H(x_u), Eq. (HApp)
 // ============================================================================
-template <bool MIXED>
+// Sum over a work-group of NT threads in a fixed order; result to all threads.
+template <int NT>
+__device__ double block_sum(double x, double* sh) {
+  constexpr int NW = NT / 64;
+  x = wave_sum(x);
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  __syncthreads();
+  if (l == 0) sh[w] = x;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
+// One work-group per row.  A row of n >= ENT_WIDE_N samples is spread over
+// W = 1024 threads, a shorter one over W = 256: thread tid takes the samples
+// k = tid + W i (binary32 sums of at most 32 of them in the mixed mode), then
+// a fixed-order reduction.  W depends only on the data set's own n (threads
+// beyond W add exact zeros), so a data set gets the same bits in any launch
+// width, alone or in a batch.
+constexpr int64_t ENT_WIDE_N = 8192;
+
+template <bool MIXED, int NT>
 __device__ __forceinline__ void k_entropy_body(const Dev& d, int t) {
   const int r = rows_left(d, t);
   if ((int)blockIdx.x >= r || r < 2 || halted(d.ctl)) return;
@@ -403,45 +427,57 @@ __device__ __forceinline__ void k_entropy_body(const Dev& d, int t) {
   const int64_t n = d.n;
   double* __restrict__ H = d.H;
   double* __restrict__ eH = d.eH;
-  __shared__ double sh[4];
+  __shared__ double sh[NT / 64];
   const double* z = d.Z[buf] + (int64_t)blockIdx.x * d.ldz;
   const double dz = d.dsc[buf][blockIdx.x];
+  const int W = NT >= 1024 && n >= ENT_WIDE_N ? 1024 : 256;
   double lc = 0.0, g = 0.0;
-  if constexpr (MIXED) {
-    const float ca = -2.0f * LOG2E_F, cg = -0.5f * LOG2E_F;
-    int64_t k = threadIdx.x;
-    while (k < n) {
-      float flc = 0.f, fg = 0.f;
-      for (int c = 0; c < 32 && k < n; ++c, k += 256) terms_mixed((float)(dz * z[k]), ca, cg, flc, fg);
-      lc += (double)flc * LN2;
-      g += (double)fg;
+  if ((int)threadIdx.x < W) {
+    if constexpr (MIXED) {
+      const float ca = -2.0f * LOG2E_F, cg = -0.5f * LOG2E_F;
+      int64_t k = threadIdx.x;
+      while (k < n) {
+        float flc = 0.f, fg = 0.f;
+#pragma unroll 4
+        for (int c = 0; c < 32; ++c, k += W)
+          if (k < n) terms_mixed((float)(dz * z[k]), ca, cg, flc, fg);
+        lc += (double)flc * LN2;
+        g += (double)fg;
+      }
+    } else {
+#pragma unroll 4
+      for (int64_t k = threadIdx.x; k < n; k += W) terms_f64(dz * z[k], lc, g);
     }
-  } else {
-    for (int64_t k = threadIdx.x; k < n; k += 256) terms_f64(dz * z[k], lc, g);
   }
-  lc = block_sum256(lc, sh);
-  g = block_sum256(g, sh);
+  lc = block_sum<NT>(lc, sh);
+  g = block_sum<NT>(g, sh);
   if (threadIdx.x == 0) {
     H[blockIdx.x] = happ_from_sums(lc, g, (double)n);
     eH[blockIdx.x] = MIXED ? happ_err_mixed(lc, g, (double)n) : 0.0;
   }
 }
 
-template <bool MIXED>
-__global__ __launch_bounds__(256) void k_entropy(const Dev* __restrict__ devs, const Dev one, int t) {
+template <bool MIXED, int NT>
+__global__ __launch_bounds__(NT) void k_entropy(const Dev* __restrict__ devs, const Dev one, int t) {
   if (devs)
-    k_entropy_body<MIXED>(devs[blockIdx.z], t);
+    k_entropy_body<MIXED, NT>(devs[blockIdx.z], t);
   else
-    k_entropy_body<MIXED>(one, t);
+    k_entropy_body<MIXED, NT>(one, t);
 }
 
 hipError_t launch_entropy(const Batch& b, int t, hipStream_t s) {
   const int r = b.p_max - t;
   if (r < 2) return hipSuccess;
-  if (b.mixed)
-    hipLaunchKernelGGL(k_entropy<true>, dim3(r, 1, b.count), dim3(256), 0, s, DEVS(b), t);
+  const dim3 g(r, 1, b.count);
+  const bool wide = b.n_max >= ENT_WIDE_N;
+  if (b.mixed && wide)
+    hipLaunchKernelGGL((k_entropy<true, 1024>), g, dim3(1024), 0, s, DEVS(b), t);
+  else if (b.mixed)
+    hipLaunchKernelGGL((k_entropy<true, 256>), g, dim3(256), 0, s, DEVS(b), t);
+  else if (wide)
+    hipLaunchKernelGGL((k_entropy<false, 1024>), g, dim3(1024), 0, s, DEVS(b), t);
   else
-    hipLaunchKernelGGL(k_entropy<false>, dim3(r, 1, b.count), dim3(256), 0, s, DEVS(b), t);
+    hipLaunchKernelGGL((k_entropy<false, 256>), g, dim3(256), 0, s, DEVS(b), t);
   return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ def _same(b, s, tag):
 def _mixed_batch(seed):
     rng = np.random.default_rng(seed)
     sets = []
-    for k, (p, n) in enumerate([(12, 1500), (40, 3000), (9, 700), (67, 5000), (25, 2048), (2, 300)]):
+    for k, (p, n) in enumerate([(12, 1500), (40, 3000), (9, 700), (67, 5000), (25, 9000), (2, 300)]):
         ds = synth.lingam_dataset(p, n, 0.2, "mixed", rng=np.random.default_rng(seed * 100 + k))
         sets.append(ds.X)
     base = synth.lingam_dataset(30, 4000, 0.15, "laplace", rng=np.random.default_rng(seed + 7)).X
