@@ -252,6 +252,7 @@ Dev alloc_set(Allocs& al, int64_t n, int64_t p, const Plan& pl, const lingam_opt
   d.forced_len = o.forced_len;
   int32_t* forced_dev = al.get<int32_t>(std::max<size_t>(1, (size_t)o.forced_len));
   d.forced = forced_dev;
+  d.pair_slots = al.get<unsigned long long>(2 * PAIR_SLOTS);
   d.band_k0 = pl.band_blocks;
   d.band_adapt = o.band_blocks > 0 ? 0 : 1;
   return d;
@@ -274,6 +275,7 @@ void init_set(const Dev& d, const lingam_opts& o, int limit, hipStream_t s, std:
   HIPCHK(launch_fill(d.Terr, (int64_t)pp, NAN, s));
   if (d.Mrec) HIPCHK(launch_fill(d.Mrec, (int64_t)d.rec * (int64_t)pp, NAN, s));
   HIPCHK(launch_fill_u8(reinterpret_cast<uint8_t*>(d.order), (int64_t)(4 * P), 0xff, s));
+  HIPCHK(launch_fill_u8(reinterpret_cast<uint8_t*>(d.pair_slots), (int64_t)(2 * PAIR_SLOTS * 8), 0, s));
   (void)limit;
 }
 
@@ -396,7 +398,10 @@ struct Fit {
 void copy_results(const Dev& d, const Ctl& c, int64_t n, lingam_result* out, hipStream_t s) {
   const size_t P = (size_t)d.p, pp = P * P;
   std::vector<int32_t> order(P);
+  std::vector<unsigned long long> slots(2 * PAIR_SLOTS);
   HIPCHK(hipMemcpyAsync(order.data(), d.order, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(slots.data(), d.pair_slots, sizeof(unsigned long long) * 2 * PAIR_SLOTS,
+                        hipMemcpyDeviceToHost, s));
   if (out->T) HIPCHK(hipMemcpyAsync(out->T, d.Tall, sizeof(double) * pp, hipMemcpyDeviceToHost, s));
   if (out->T_state) HIPCHK(hipMemcpyAsync(out->T_state, d.Tstate, pp, hipMemcpyDeviceToHost, s));
   if (out->H) HIPCHK(hipMemcpyAsync(out->H, d.Hall, sizeof(double) * pp, hipMemcpyDeviceToHost, s));
@@ -406,9 +411,14 @@ void copy_results(const Dev& d, const Ctl& c, int64_t n, lingam_result* out, hip
     HIPCHK(hipMemcpyAsync(out->M, d.Mrec, sizeof(double) * pp * d.rec, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   std::memcpy(out->order, order.data(), sizeof(int32_t) * P);
-  out->pairs_evaluated = c.pairs_evaluated;
-  out->pair_samples = c.pairs_evaluated * (uint64_t)n;
-  out->pairs_computed = c.pairs_computed;
+  uint64_t ev = 0, comp = 0;
+  for (int k = 0; k < PAIR_SLOTS; ++k) {
+    ev += slots[(size_t)k];
+    comp += slots[(size_t)(PAIR_SLOTS + k)];
+  }
+  out->pairs_evaluated = ev;
+  out->pair_samples = ev * (uint64_t)n;
+  out->pairs_computed = comp;
   out->threshold_rounds = c.rounds_total;
   out->bands = c.bands_total;
   int it = 0;
@@ -496,7 +506,7 @@ uint64_t lingam_workspace_size(int64_t n, int64_t p, const lingam_opts* o) {
   b += 2 * pp * 8 + 2 * P * 8;          // rounding bounds: per test, per score record, eH, eT
   b += (uint64_t)op.record_M_iters * pp * 8;
   if (!op.x_on_device) b += P * (uint64_t)n * (op.x_dtype == 1 ? 4 : 8);
-  b += sizeof(Ctl) + sizeof(Dev);
+  b += sizeof(Ctl) + sizeof(Dev) + 2 * PAIR_SLOTS * 8;
   return b;
 }
 

@@ -647,6 +647,7 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
   const int lo = xcd * ipx, hi = min(items, lo + ipx);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int lane = threadIdx.x % 64;
+  unsigned n_eval = 0, n_comp = 0;  // pairs this wave evaluated / computed
   for (int item = lo + (int)(blockIdx.x / 8); item < hi; item += per_xcd) {
   const int g = item % nrg;
   const int tb = (item / nrg) % ntb;
@@ -822,11 +823,17 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
     pend[(int64_t)v * p + w] = 1;
     pend[(int64_t)w * p + v] = 1;
   }
-  if (chunk == 0 && lane == 0 && mask) {
-    atomicAdd(&ctl->pairs_evaluated, (unsigned long long)__popc(mask));
-    atomicAdd(&ctl->pairs_computed, (unsigned long long)TPW);
+  if (chunk == 0 && mask) {
+    n_eval += (unsigned)__popc(mask);
+    n_comp += TPW;
   }
   __syncthreads();  // s_mask, s_sc and lds are reused by the next item
+  }
+  // one add per wave, on addresses spread over the slots
+  if (lane == 0 && n_comp) {
+    const int slot = (int)((blockIdx.x * NW + wave) % PAIR_SLOTS);
+    atomicAdd(&d.pair_slots[slot], (unsigned long long)n_eval);
+    atomicAdd(&d.pair_slots[PAIR_SLOTS + slot], (unsigned long long)n_comp);
   }
 }
 

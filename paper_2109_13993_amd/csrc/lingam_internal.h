@@ -19,6 +19,7 @@ constexpr int CHUNK_DEFAULT = 2048;
 constexpr int CHUNK_MAX_MIXED = 2048;
 // Degeneracy guard on 1 - corr^2 of an evaluated pair (and row variance).
 constexpr double DEGEN_EPS = 1e-12;
+constexpr int PAIR_SLOTS = 2048;
 
 enum Status : int32_t { ST_OK = 0, ST_INVALID = 1, ST_NONFINITE = 2, ST_DEGENERATE = 3 };
 
@@ -40,8 +41,6 @@ struct Ctl {
   int32_t iter_bands;     // bands run in the current iteration
   int32_t win_bands;      // most bands of one iteration since the host last looked
   double last_root_S;     // score of the previous iteration's root (adaptive gamma0)
-  unsigned long long pairs_evaluated;
-  unsigned long long pairs_computed;
   unsigned long long rounds_total;
   unsigned long long bands_total;
 };
@@ -57,6 +56,10 @@ struct Dev {
   int layout = 0;            // 0 = p x n (row = variable), 1 = n x p
   int nchunk = 1;            // sample chunks of the pair kernel, ceil(n / chunk)
   int limit = 0;             // iterations to run (p, or fewer when max_roots is set)
+  // Pair counters, spread over PAIR_SLOTS addresses (slot = wave % PAIR_SLOTS)
+  // so that their atomics do not queue on one address: [0, PAIR_SLOTS)
+  // evaluated pairs, [PAIR_SLOTS, 2 PAIR_SLOTS) pairs computed.  Summed by the host.
+  unsigned long long* pair_slots = nullptr;
   int band_k0 = 4;           // target blocks of an iteration's first band (every block: no threshold)
   int band_adapt = 1;        // 1 = size later bands from the alive count, 0 = band_k0 blocks each
   int64_t ldz = 0;           // row stride of Z (doubles), multiple of 64
