@@ -692,7 +692,10 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
     double sj = 1.0;
     if (mask >> j & 1u) {
       const int w = B * TB + j0 + j;
-      const double b = Sig[(int64_t)v * p + w] * dsc[v] * dsc[w];
+      // formed in ascending variable order, so a pair gets the same bits
+      // whichever of its variables is the row
+      const int lo = min(v, w), hi = max(v, w);
+      const double b = Sig[(int64_t)lo * p + hi] * dsc[lo] * dsc[hi];
       const double om = 1.0 - b * b;
       if (!(om > DEGEN_EPS)) {
         if (lane == 0) raise_error(ctl, ST_DEGENERATE, idx[v], idx[w]);
