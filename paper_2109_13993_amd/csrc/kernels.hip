@@ -857,9 +857,9 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(const Dev* _
 // that the CUs hold several at a time, so the first band of an iteration
 // (every row, one target block) and the later bands (few rows, several
 // blocks) both spread over the whole device.  The first band's grid may
-// take many generations of groups; later bands are bounded to one.  The
-// FP64 variant uses more rows per group because its terms need more
-// registers per lane.
+// take many generations of groups; later bands are bounded to one.  FP64
+// mode: one row per group, its 8 targets over 4 waves of 2 (its terms need
+// more registers per lane), later bands bounded to two generations.
 template <bool MIXED, int RG, int TPW, int PS>
 static int resident_groups() {
   static std::atomic<int> cached{0};
@@ -905,9 +905,9 @@ hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense,
   else if (b.mixed)
     launch_pair_shape<true, 2, 4, 256>(b, t, a, ntb_hint, s, 1);
   else if (dense)
-    launch_pair_shape<false, 4, 8, 256>(b, t, a, ntb_hint, s, 1 << 16);
+    launch_pair_shape<false, 1, 2, 256>(b, t, a, ntb_hint, s, 1 << 16);
   else
-    launch_pair_shape<false, 2, 2, 512>(b, t, a, ntb_hint, s, 1);
+    launch_pair_shape<false, 1, 2, 256>(b, t, a, ntb_hint, s, 2);
   return hipGetLastError();
 }
 
