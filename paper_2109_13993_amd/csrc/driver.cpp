@@ -173,8 +173,9 @@ void reset_result(lingam_result* out, int64_t p, int rec) {
   out->status = LINGAM_OK;
 }
 
-// Optional timing of the pair-kernel launches: an event pair around each
-// launch on the same stream, summed at the end of the call.
+// Optional timing of the pair-kernel launches: a pair of events that take
+// each launch's own start and end time on its stream, summed at the end of
+// the call.
 struct PairTimer {
   bool on = false;
   std::vector<hipEvent_t> ev;
@@ -297,9 +298,8 @@ struct Fit {
 
   void pair(int t, const BandArgs& a, bool dense, int ntb_hint) {
     if (timer && timer->on) {
-      HIPCHK(hipEventRecord(timer->next(), s));
-      HIPCHK(launch_pair_band(b, t, a, dense ? 1 : 0, ntb_hint, s));
-      HIPCHK(hipEventRecord(timer->next(), s));
+      hipEvent_t e0 = timer->next(), e1 = timer->next();
+      HIPCHK(launch_pair_band(b, t, a, dense ? 1 : 0, ntb_hint, s, e0, e1));
       ++timer->launches;
     } else {
       HIPCHK(launch_pair_band(b, t, a, dense ? 1 : 0, ntb_hint, s));
@@ -311,7 +311,9 @@ struct Fit {
     const int r = b.p_max - t;
     const int nb = (r + TB - 1) / TB;
     const int hint = first ? (threshold ? std::min(pl.band_blocks, nb) : nb) : nb;
-    const BandArgs a{pl.chunk};
+    BandArgs a{pl.chunk, 1, 1, BAND_TARGET_DEFAULT};
+    pair_band_shape(b, a.rows_per_group, a.groups);
+    if (b.count == 1 && b.mixed) a.band_target = BAND_TARGET_SINGLE_MIXED;
     pair(t, a, first, hint);
     HIPCHK(launch_score(b, t, a, gmult, first ? 1 : 0, hint, s));
   }
@@ -331,10 +333,9 @@ struct Fit {
   }
 
   void queue_tail(int t) {
-    HIPCHK(launch_finish_iter(b, t, s));
-    if (t < rec) HIPCHK(launch_record_M(b, t, s));
     const bool refresh = refresh_every > 0 && ((t + 1) % refresh_every == 0);
-    HIPCHK(launch_update(b, t, refresh ? 1 : 0, s));
+    HIPCHK(launch_iter_end(b, t, refresh ? 1 : 0, s));
+    if (t < rec) HIPCHK(launch_record_M(b, t, s));
   }
 
   // iteration t of every data set that has one (p - t >= 2 and t < its limit);
@@ -344,8 +345,7 @@ struct Fit {
     for (size_t k = 0; k < ps.size(); ++k) any_last |= (ps[k] - t == 1 && t < limits[k]);
     if (any_last) HIPCHK(launch_last(b, t, s));
     if (b.p_max - t < 2) return;
-    HIPCHK(launch_entropy(b, t, s));
-    HIPCHK(launch_iter_init(b, t, threshold ? gamma0 : INFINITY, GAMMA_ADAPT, threshold ? 1 : 0, s));
+    HIPCHK(launch_iter_start(b, t, threshold ? gamma0 : INFINITY, GAMMA_ADAPT, threshold ? 1 : 0, s));
     queue_rounds(t);
     queue_tail(t);
   }

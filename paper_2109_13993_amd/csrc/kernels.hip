@@ -9,7 +9,8 @@
 //                  binary64 matrix cores (v_mfma_f64_16x16x4f64); also the
 //                  refresh of Sigma after each UpdateData.
 //   k_entropy      H(x_u) of Eq. (HApp) for every remaining variable (the two
-//                  per-variable terms of Eq. (Itest), computed once per iteration).
+//                  per-variable terms of Eq. (Itest), computed once per
+//                  iteration), and the iteration's set-up.
 //   k_pair_band    Compare for a band of pair tiles (Alg. 2 body, Eq. (Itest),
 //                  Eq. (HApp)): the residuals r_i^(j) and r_j^(i), normalised by
 //                  1/sqrt(1 - b^2) (Eq. var_update), are formed on the fly from two
@@ -21,8 +22,11 @@
 //                  work-group applies the termination test and the threshold
 //                  update of the Scheduler (Alg. 6 / Sec. 4.3) and picks the root.
 //   k_update_*     UpdateData and UpdateCovMat (Sec. 3.4): rank-1 update of the
-//                  remaining rows and of Sigma, compacting out the root.
+//                  remaining rows and of Sigma, compacting out the root; the
+//                  iteration's results are recorded first.
 #include "lingam_internal.h"
+
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <atomic>
@@ -393,6 +397,49 @@ hipError_t launch_gram(const Batch& b, int buf, int t, hipStream_t s) {
 }
 
 // ============================================================================
+// iteration set-up: M = "not evaluated", S = 0, everyone below the threshold
+// ============================================================================
+// Row x's share, done by the work-group that also forms the row's entropy:
+// its tests (row x of M and of the pending flags), its score and threshold
+// state; the group of row 0 also sets the iteration's control fields.
+// gamma0 > 0: that initial threshold in every iteration; gamma0 <= 0:
+// adaptive, `adapt` times the previous iteration's root score (the first
+// iteration and a zero previous score use 1e-6).
+__device__ __forceinline__ void iter_init_row(const Dev& d, int t, int x, double gamma0, double adapt,
+                                              int threshold) {
+  const int r = rows_left(d, t), p = d.p;
+  Ctl* ctl = d.ctl;
+  double* M = d.M + (int64_t)x * p;
+  uint8_t* pend = d.pend + (int64_t)x * p;
+  for (int w = threadIdx.x; w < r; w += blockDim.x) {
+    M[w] = __builtin_nan("");
+    pend[w] = 0;
+  }
+  if (threadIdx.x == 0) {
+    d.S[x] = 0.0;
+    d.alive[x] = 1;
+    d.complete[x] = 0;
+    d.alive_list[x] = x;
+  }
+  if (x == 0 && threadIdx.x == 0) {
+    double g = gamma0;
+    if (!(g > 0.0)) {
+      const double prev = ctl->last_root_S;
+      g = prev > 0.0 ? adapt * prev : 1e-6;
+    }
+    ctl->gamma = g;
+    ctl->done = 0;
+    ctl->root = -1;
+    ctl->round = 0;
+    ctl->n_alive = r;
+    const int nb = (r + TB - 1) / TB;
+    ctl->tb_next = 0;
+    ctl->ntb_next = threshold ? min(d.band_k0, nb) : nb;
+    ctl->iter_bands = 0;
+  }
+}
+
+// ============================================================================
 // a3: per-variable entropy H(x_u), Eq. (HApp)
 // ============================================================================
 // Sum over a work-group of NT threads in a fixed order; result to all threads.
@@ -420,9 +467,10 @@ __device__ double block_sum(double x, double* sh) {
 constexpr int64_t ENT_WIDE_N = 8192;
 
 template <bool MIXED, int NT>
-__device__ __forceinline__ void k_entropy_body(const Dev& d, int t) {
+__device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma0, double adapt, int threshold) {
   const int r = rows_left(d, t);
   if ((int)blockIdx.x >= r || r < 2 || halted(d.ctl)) return;
+  iter_init_row(d, t, (int)blockIdx.x, gamma0, adapt, threshold);
   const int buf = t & 1;
   const int64_t n = d.n;
   double* __restrict__ H = d.H;
@@ -458,92 +506,27 @@ __device__ __forceinline__ void k_entropy_body(const Dev& d, int t) {
 }
 
 template <bool MIXED, int NT>
-__global__ __launch_bounds__(NT) void k_entropy(const Dev* __restrict__ devs, const Dev one, int t) {
+__global__ __launch_bounds__(NT) void k_entropy(const Dev* __restrict__ devs, const Dev one, int t, double gamma0,
+                                                double adapt, int threshold) {
   if (devs)
-    k_entropy_body<MIXED, NT>(devs[blockIdx.z], t);
+    k_entropy_body<MIXED, NT>(devs[blockIdx.z], t, gamma0, adapt, threshold);
   else
-    k_entropy_body<MIXED, NT>(one, t);
+    k_entropy_body<MIXED, NT>(one, t, gamma0, adapt, threshold);
 }
 
-hipError_t launch_entropy(const Batch& b, int t, hipStream_t s) {
+hipError_t launch_iter_start(const Batch& b, int t, double gamma0, double adapt, int threshold, hipStream_t s) {
   const int r = b.p_max - t;
   if (r < 2) return hipSuccess;
   const dim3 g(r, 1, b.count);
   const bool wide = b.n_max >= ENT_WIDE_N;
   if (b.mixed && wide)
-    hipLaunchKernelGGL((k_entropy<true, 1024>), g, dim3(1024), 0, s, DEVS(b), t);
+    hipLaunchKernelGGL((k_entropy<true, 1024>), g, dim3(1024), 0, s, DEVS(b), t, gamma0, adapt, threshold);
   else if (b.mixed)
-    hipLaunchKernelGGL((k_entropy<true, 256>), g, dim3(256), 0, s, DEVS(b), t);
+    hipLaunchKernelGGL((k_entropy<true, 256>), g, dim3(256), 0, s, DEVS(b), t, gamma0, adapt, threshold);
   else if (wide)
-    hipLaunchKernelGGL((k_entropy<false, 1024>), g, dim3(1024), 0, s, DEVS(b), t);
+    hipLaunchKernelGGL((k_entropy<false, 1024>), g, dim3(1024), 0, s, DEVS(b), t, gamma0, adapt, threshold);
   else
-    hipLaunchKernelGGL((k_entropy<false, 256>), g, dim3(256), 0, s, DEVS(b), t);
-  return hipGetLastError();
-}
-
-// ============================================================================
-// iteration set-up: M = "not evaluated", S = 0, everyone below the threshold
-// ============================================================================
-// gamma0 > 0: that initial threshold in every iteration; gamma0 <= 0: adaptive,
-// `adapt` times the previous iteration's root score (the first iteration and a
-// zero previous score use 1e-6).
-__device__ __forceinline__ void k_iter_init_body(const Dev& d, int t, double gamma0, double adapt,
-                                                 int threshold) {
-  const int r = rows_left(d, t), p = d.p;
-  Ctl* ctl = d.ctl;
-  if (r < 2 || halted(ctl)) return;
-  double* M = d.M;
-  uint8_t* pend = d.pend;
-  double* S = d.S;
-  uint8_t* alive = d.alive;
-  uint8_t* complete = d.complete;
-  int32_t* alive_list = d.alive_list;
-  const int64_t total = (int64_t)r * r;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int x = (int)(e / r), w = (int)(e % r);
-    M[(int64_t)x * p + w] = __builtin_nan("");
-    pend[(int64_t)x * p + w] = 0;
-  }
-  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < r; x += gridDim.x * blockDim.x) {
-    S[x] = 0.0;
-    alive[x] = 1;
-    complete[x] = 0;
-    alive_list[x] = x;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double g = gamma0;
-    if (!(g > 0.0)) {
-      const double prev = ctl->last_root_S;
-      g = prev > 0.0 ? adapt * prev : 1e-6;
-    }
-    ctl->gamma = g;
-    ctl->done = 0;
-    ctl->root = -1;
-    ctl->round = 0;
-    ctl->n_alive = r;
-    const int nb = (r + TB - 1) / TB;
-    ctl->tb_next = 0;
-    ctl->ntb_next = threshold ? min(d.band_k0, nb) : nb;
-    ctl->iter_bands = 0;
-  }
-}
-
-__global__ void k_iter_init(const Dev* __restrict__ devs, const Dev one, int t, double gamma0, double adapt,
-                            int threshold) {
-  if (devs)
-    k_iter_init_body(devs[blockIdx.z], t, gamma0, adapt, threshold);
-  else
-    k_iter_init_body(one, t, gamma0, adapt, threshold);
-}
-
-hipError_t launch_iter_init(const Batch& b, int t, double gamma0, double adapt, int threshold, hipStream_t s) {
-  const int r = b.p_max - t;
-  if (r < 2) return hipSuccess;
-  const int64_t total = (int64_t)r * r;
-  int blocks = (int)std::min<int64_t>(std::max(8, 1024 / b.count), (total + 255) / 256);
-  hipLaunchKernelGGL(k_iter_init, dim3(std::max(blocks, 1), 1, b.count), dim3(256), 0, s, DEVS(b), t, gamma0, adapt,
-                     threshold);
+    hipLaunchKernelGGL((k_entropy<false, 256>), g, dim3(256), 0, s, DEVS(b), t, gamma0, adapt, threshold);
   return hipGetLastError();
 }
 
@@ -701,7 +684,7 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
         if (lane == 0) raise_error(ctl, ST_DEGENERATE, idx[v], idx[w]);
       } else {
         bj[j] = b;
-        sj = 1.0 / sqrt(om);
+        sj = rsqrt(om);
       }
     }
     if (lane == j) s_sc[wave][j] = sj;
@@ -879,8 +862,13 @@ static int resident_groups() {
 }
 
 template <bool MIXED, int RG, int TPW, int PS>
+static int groups_per_set(const Batch& b, int max_waves) {
+  return std::max(8, max_waves * resident_groups<MIXED, RG, TPW, PS>() / b.count);
+}
+
+template <bool MIXED, int RG, int TPW, int PS>
 static void launch_pair_shape(const Batch& b, int t, const BandArgs& a, int ntb_hint, hipStream_t s,
-                              int max_waves) {
+                              int max_waves, hipEvent_t ev0, hipEvent_t ev1) {
   const int r = b.p_max - t;
   const int nb = (r + TB - 1) / TB;
   const int ntb = std::max(1, std::min(ntb_hint, nb));  // most target blocks the band can have
@@ -889,25 +877,40 @@ static void launch_pair_shape(const Batch& b, int t, const BandArgs& a, int ntb_
   // at most max_waves generations of resident work-groups over the batch;
   // sparse bands use one, so no work-group waits for a slot only to find
   // nothing to do
-  const int per_set = std::max(8, max_waves * resident_groups<MIXED, RG, TPW, PS>() / b.count);
+  const int per_set = groups_per_set<MIXED, RG, TPW, PS>(b, max_waves);
   const int G = std::min(ntb * b.nchunk_max * nrg, per_set);  // items when every row is alive
   const int grid = (G + 7) / 8 * 8;
   const dim3 g(grid, 1, b.count), blk(64 * RG * (TB / TPW));
+  // the events, when given, take the launch's own start and end times, so
+  // they add no packets of their own between the kernels
   if (b.count == 1)
-    hipLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS, false>), g, blk, 0, s, nullptr, b.one, t, a);
+    hipExtLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS, false>), g, blk, 0, s, ev0, ev1, 0,
+                          (const Dev*)nullptr, b.one, t, a);
   else
-    hipLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS, true>), g, blk, 0, s, b.dd, b.one, t, a);
+    hipExtLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS, true>), g, blk, 0, s, ev0, ev1, 0,
+                          (const Dev*)b.dd, b.one, t, a);
 }
 
-hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense, int ntb_hint, hipStream_t s) {
+void pair_band_shape(const Batch& b, int& rows_per_group, int& groups) {
+  if (b.mixed) {
+    rows_per_group = 2;
+    groups = groups_per_set<true, 2, 4, 256>(b, 1);
+  } else {
+    rows_per_group = 1;
+    groups = groups_per_set<false, 1, 2, 256>(b, 2);
+  }
+}
+
+hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense, int ntb_hint, hipStream_t s,
+                            hipEvent_t ev0, hipEvent_t ev1) {
   if (b.mixed && dense)
-    launch_pair_shape<true, 2, 4, 256>(b, t, a, ntb_hint, s, 1 << 16);
+    launch_pair_shape<true, 2, 4, 256>(b, t, a, ntb_hint, s, 1 << 16, ev0, ev1);
   else if (b.mixed)
-    launch_pair_shape<true, 2, 4, 256>(b, t, a, ntb_hint, s, 1);
+    launch_pair_shape<true, 2, 4, 256>(b, t, a, ntb_hint, s, 1, ev0, ev1);
   else if (dense)
-    launch_pair_shape<false, 1, 2, 256>(b, t, a, ntb_hint, s, 1 << 16);
+    launch_pair_shape<false, 1, 2, 256>(b, t, a, ntb_hint, s, 1 << 16, ev0, ev1);
   else
-    launch_pair_shape<false, 1, 2, 256>(b, t, a, ntb_hint, s, 2);
+    launch_pair_shape<false, 1, 2, 256>(b, t, a, ntb_hint, s, 2, ev0, ev1);
   return hipGetLastError();
 }
 
@@ -1152,8 +1155,18 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
       const int left = nb - (tb0 + ntb);
       int k = d.band_k0;
       if (d.band_adapt) {
-        const double want = BAND_TARGET_PAIR_SAMPLES / ((double)TB * (double)max(ctl->n_alive, 1) * n);
-        k = want >= (double)left ? left : max(k, (int)ceil(want));
+        const int m_next = max(ctl->n_alive, 1);
+        const double want = a.band_target / ((double)TB * (double)m_next * n);
+        // whole rounds of the work-groups: a target block brings one item
+        // per row group and chunk, and a band whose items overrun a round
+        // by a few leaves most groups idle for a second one
+        const int per_block = (m_next + a.rows_per_group - 1) / a.rows_per_group * nchunk;
+        const int fill = a.groups / per_block;  // blocks that fill one round
+        if (fill >= 1)
+          k = fill * max(1, (int)ceil(want / (double)fill));
+        else
+          k = max(k, (int)ceil(want));
+        if (want >= (double)left) k = left;
       }
       ctl->tb_next = tb0 + ntb;
       ctl->ntb_next = min(k, left);
@@ -1191,6 +1204,36 @@ __global__ void k_window_reset(const Dev* __restrict__ devs, const Dev one) {
 // Clear the per-window band maximum of every data set (read by the host).
 hipError_t launch_window_reset(const Batch& b, hipStream_t s) {
   hipLaunchKernelGGL(k_window_reset, dim3(1, 1, b.count), dim3(1), 0, s, DEVS(b));
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ void k_record_M_body(const Dev& d, int t) {
+  const int r = rows_left(d, t), p = d.p;
+  if (r < 2 || t >= d.rec || halted(d.ctl)) return;
+  const double* __restrict__ M = d.M;
+  const int32_t* __restrict__ idx = d.idx[t & 1];
+  double* __restrict__ Mrec = d.Mrec + (int64_t)t * p * p;
+  const int64_t total = (int64_t)r * r;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(e / r), w = (int)(e % r);
+    Mrec[(int64_t)idx[x] * p + idx[w]] = M[(int64_t)x * p + w];
+  }
+}
+
+__global__ void k_record_M(const Dev* __restrict__ devs, const Dev one, int t) {
+  if (devs)
+    k_record_M_body(devs[blockIdx.z], t);
+  else
+    k_record_M_body(one, t);
+}
+
+hipError_t launch_record_M(const Batch& b, int t, hipStream_t s) {
+  const int r = b.p_max - t;
+  if (r < 2) return hipSuccess;
+  const int64_t total = (int64_t)r * r;
+  int blocks = (int)std::min<int64_t>(1024, (total + 255) / 256);
+  hipLaunchKernelGGL(k_record_M, dim3(std::max(blocks, 1), 1, b.count), dim3(256), 0, s, DEVS(b), t);
   return hipGetLastError();
 }
 
@@ -1233,49 +1276,6 @@ __device__ __forceinline__ void k_finish_iter_body(const Dev& d, int t) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_finish_iter(const Dev* __restrict__ devs, const Dev one, int t) {
-  if (devs)
-    k_finish_iter_body(devs[blockIdx.z], t);
-  else
-    k_finish_iter_body(one, t);
-}
-
-hipError_t launch_finish_iter(const Batch& b, int t, hipStream_t s) {
-  if (b.p_max - t < 2) return hipSuccess;
-  hipLaunchKernelGGL(k_finish_iter, dim3(1, 1, b.count), dim3(256), 0, s, DEVS(b), t);
-  return hipGetLastError();
-}
-
-__device__ __forceinline__ void k_record_M_body(const Dev& d, int t) {
-  const int r = rows_left(d, t), p = d.p;
-  if (r < 2 || t >= d.rec || halted(d.ctl)) return;
-  const double* __restrict__ M = d.M;
-  const int32_t* __restrict__ idx = d.idx[t & 1];
-  double* __restrict__ Mrec = d.Mrec + (int64_t)t * p * p;
-  const int64_t total = (int64_t)r * r;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int x = (int)(e / r), w = (int)(e % r);
-    Mrec[(int64_t)idx[x] * p + idx[w]] = M[(int64_t)x * p + w];
-  }
-}
-
-__global__ void k_record_M(const Dev* __restrict__ devs, const Dev one, int t) {
-  if (devs)
-    k_record_M_body(devs[blockIdx.z], t);
-  else
-    k_record_M_body(one, t);
-}
-
-hipError_t launch_record_M(const Batch& b, int t, hipStream_t s) {
-  const int r = b.p_max - t;
-  if (r < 2) return hipSuccess;
-  const int64_t total = (int64_t)r * r;
-  int blocks = (int)std::min<int64_t>(1024, (total + 255) / 256);
-  hipLaunchKernelGGL(k_record_M, dim3(std::max(blocks, 1), 1, b.count), dim3(256), 0, s, DEVS(b), t);
-  return hipGetLastError();
-}
-
 // ============================================================================
 // a7: UpdateData and UpdateCovMat (Sec. 3.4), compacting out the root
 // ============================================================================
@@ -1309,8 +1309,12 @@ __global__ __launch_bounds__(256) void k_update_rows(const Dev* __restrict__ dev
     k_update_rows_body(one, t);
 }
 
+// Work-group 0 first records the iteration's results (or halts an iteration
+// the queued bands did not finish); then every group takes its share of
+// UpdateCovMat.
 __device__ __forceinline__ void k_update_sigma_body(const Dev& d, int t, int recursion) {
   const int r = rows_left(d, t), p = d.p;
+  if (blockIdx.x == 0) k_finish_iter_body(d, t);
   const Ctl* ctl = d.ctl;
   if (r < 2 || halted(ctl) || !ctl->done) return;
   const int buf = t & 1;
@@ -1353,7 +1357,7 @@ __global__ __launch_bounds__(256) void k_update_sigma(const Dev* __restrict__ de
     k_update_sigma_body(one, t, recursion);
 }
 
-hipError_t launch_update(const Batch& b, int t, int refresh, hipStream_t s) {
+hipError_t launch_iter_end(const Batch& b, int t, int refresh, hipStream_t s) {
   const int rn = b.p_max - t - 1;
   if (rn <= 0) return hipSuccess;
   const int xblocks = (int)std::min<int64_t>(64, (b.n_max + 255) / 256);

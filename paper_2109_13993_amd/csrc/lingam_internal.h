@@ -100,8 +100,14 @@ struct Dev {
 
 // Samples per pair-kernel band that later bands of round 0 aim at: their
 // target-block count is chosen so that (alive rows) x (targets) x n is
-// about this, between band_k0 and the blocks left.
-constexpr double BAND_TARGET_PAIR_SAMPLES = 4e7;
+// about this, rounded up to whole rounds of the work-groups when it fills
+// at least one, between band_k0 and the blocks left.  A single mixed-mode
+// search takes larger bands (its per-band overhead weighs more against its
+// fast pair kernel); FP64 searches and batches, whose launches carry more
+// work per band, take smaller ones.  Chosen by measurement at p=500,
+// n=20000 and on the batch workloads.
+constexpr double BAND_TARGET_SINGLE_MIXED = 6e7;
+constexpr double BAND_TARGET_DEFAULT = 2e7;
 
 // Parameters of one band launch of the pair kernel.  Which target blocks
 // the band covers is decided on the device (Ctl::tb_next, ntb_next), so
@@ -109,6 +115,9 @@ constexpr double BAND_TARGET_PAIR_SAMPLES = 4e7;
 // returns at once.
 struct BandArgs {
   int chunk;      // samples per chunk
+  int rows_per_group;  // alive rows per pair-kernel work-group
+  int groups;     // pair-kernel work-groups one data set's later bands run on
+  double band_target;  // pair-samples a later band of round 0 aims at
 };
 
 // What a launch covers: `count` data sets whose descriptors are at `dd` on
@@ -130,15 +139,24 @@ struct Batch {
 // the ping-pong buffers.
 hipError_t launch_standardize(const Batch& b, hipStream_t s);
 hipError_t launch_gram(const Batch& b, int buf, int t, hipStream_t s);
-hipError_t launch_entropy(const Batch& b, int t, hipStream_t s);
-hipError_t launch_iter_init(const Batch& b, int t, double gamma0, double adapt, int threshold, hipStream_t s);
-hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense, int ntb_hint, hipStream_t s);
+// Start of iteration t: the entropies of the remaining rows and the
+// iteration's set-up (tests not evaluated, scores 0, threshold state).
+hipError_t launch_iter_start(const Batch& b, int t, double gamma0, double adapt, int threshold, hipStream_t s);
+// Shape of the later (bounded) pair-kernel bands of a launch over b: rows
+// per work-group and the work-groups one data set gets.
+void pair_band_shape(const Batch& b, int& rows_per_group, int& groups);
+// ev0/ev1 (optional): events that take the start and end time of the launch
+// itself (nullptr: an untimed launch).
+hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense, int ntb_hint, hipStream_t s,
+                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_mult, int dense, int ntb_hint,
                         hipStream_t s);
 hipError_t launch_window_reset(const Batch& b, hipStream_t s);
-hipError_t launch_finish_iter(const Batch& b, int t, hipStream_t s);
 hipError_t launch_record_M(const Batch& b, int t, hipStream_t s);
-hipError_t launch_update(const Batch& b, int t, int refresh, hipStream_t s);
+// End of iteration t: its results (order, T, H, bounds; an unfinished
+// iteration halts instead), UpdateData and UpdateCovMat, and with refresh
+// the Gram of the updated rows.
+hipError_t launch_iter_end(const Batch& b, int t, int refresh, hipStream_t s);
 hipError_t launch_last(const Batch& b, int t, hipStream_t s);
 hipError_t launch_resume(const Batch& b, hipStream_t s);
 hipError_t launch_gather(const double* X, int64_t n_src, int64_t p, const int64_t* idx, int64_t n_idx,
