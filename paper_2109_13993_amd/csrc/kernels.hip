@@ -25,6 +25,7 @@
 //                  remaining rows and of Sigma, compacting out the root; the
 //                  iteration's results are recorded first.
 #include "lingam_internal.h"
+#include "fp64_math.h"
 
 #include <hip/hip_ext.h>
 
@@ -98,9 +99,10 @@ __device__ int block_or256(int x, int* sh) {
 
 // ---- element terms of Eq. (HApp) ------------------------------------------
 // FP64: log cosh(u) + log 2 = |u| + log1p(exp(-2|u|)); g(u) = u exp(-u^2/2).
+// The logarithm's argument lies in [0, 1], the range of log1p_unit.
 __device__ __forceinline__ void terms_f64(double u, double& lc, double& g) {
   const double a = fabs(u);
-  lc += a + log1p(exp(-2.0 * a));
+  lc += a + log1p_unit(exp(-2.0 * a));
   g += u * exp(-0.5 * u * u);
 }
 
@@ -1191,7 +1193,7 @@ hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_m
   // rows when every variable is alive; after the first band of an iteration
   // few are, and a smaller grid keeps idle groups from filling the launch
   const int rows = std::min(r, std::max(1, std::min(ntb_hint, nb)) * TB) + r;
-  const int cap = std::max(8, (dense ? 512 : 128) / std::min(b.count, 16));
+  const int cap = std::max(8, (dense ? 512 : 256) / std::min(b.count, 16));
   hipLaunchKernelGGL(k_score, dim3(std::min(rows, cap), 1, b.count), dim3(256), 0, s, DEVS(b), t, a, gamma_mult);
   return hipGetLastError();
 }
