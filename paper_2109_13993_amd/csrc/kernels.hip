@@ -701,31 +701,29 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
   const double* zrow = Z + (int64_t)(mask ? v : 0) * ldz;
   // this thread's share of the staged target rows: fixed rows, so their
   // scales are loaded once
+  // (a target position past the last variable, var >= r, is read from row
+  // r - 1 with scale 0, and its pairs are never kept)
   double dB[NSTG];
+  const double* srow[NSTG];
 #pragma unroll
   for (int i = 0; i < NSTG; ++i) {
-    const int var = B * TB + (i * NT + (int)threadIdx.x) / (PS / 2);
+    const int e = i * NT + (int)threadIdx.x;
+    const int var = B * TB + e / (PS / 2);
     dB[i] = var < r ? dsc[var] : 0.0;
+    srow[i] = Z + (int64_t)min(var, r - 1) * ldz + 2 * (e % (PS / 2));
   }
   double2 stg[NSTG];
   double zn[SPL];
-  // global loads of one stage into registers (only samples < kend are read,
-  // so every load stays inside its row)
+  // global loads of one stage into registers.  A stage starts at a multiple
+  // of SUB below n, and PS divides SUB, so the whole stage lies inside the
+  // row's zero-padded stride ldz = n rounded up to SUB: the loads need no
+  // bounds test (samples past n are read as padding and never summed).
+  static_assert(SUB % PS == 0, "a stage must end inside the padded row");
   auto load_stage = [&](int64_t ks) {
-    const int cnt = (int)min((int64_t)PS, kend - ks);
 #pragma unroll
-    for (int i = 0; i < NSTG; ++i) {
-      const int e = i * NT + (int)threadIdx.x;
-      const int row = e / (PS / 2), c2 = e % (PS / 2);
-      const int var = B * TB + row;
-      stg[i] = make_double2(0.0, 0.0);
-      if (var < r && 2 * c2 < cnt) stg[i] = *reinterpret_cast<const double2*>(Z + (int64_t)var * ldz + ks + 2 * c2);
-    }
+    for (int i = 0; i < NSTG; ++i) stg[i] = *reinterpret_cast<const double2*>(srow[i] + ks);
 #pragma unroll
-    for (int i = 0; i < SPL; ++i) {
-      const int k = i * 64 + lane;
-      zn[i] = mask && k < cnt ? zrow[ks + k] : 0.0;
-    }
+    for (int i = 0; i < SPL; ++i) zn[i] = zrow[ks + i * 64 + lane];
   };
 
   // accumulators: [j][0] lc(r_v), [j][1] g(r_v), [j][2] lc(r_w), [j][3] g(r_w)
@@ -1300,6 +1298,7 @@ __device__ __forceinline__ void k_update_rows_body(const Dev& d, int t) {
   const double* zr = Z + (int64_t)root * ldz;
   const double* zw = Z + (int64_t)w * ldz;
   double* zo = Zn + (int64_t)wn * ldz;
+#pragma unroll 4
   for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
     zo[k] = (dw * zw[k] - b * (dr * zr[k])) * sc;
 }
@@ -1362,7 +1361,7 @@ __global__ __launch_bounds__(256) void k_update_sigma(const Dev* __restrict__ de
 hipError_t launch_iter_end(const Batch& b, int t, int refresh, hipStream_t s) {
   const int rn = b.p_max - t - 1;
   if (rn <= 0) return hipSuccess;
-  const int xblocks = (int)std::min<int64_t>(64, (b.n_max + 255) / 256);
+  const int xblocks = (int)std::min<int64_t>(16, (b.n_max + 255) / 256);
   hipLaunchKernelGGL(k_update_rows, dim3(xblocks, rn, b.count), dim3(256), 0, s, DEVS(b), t);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
