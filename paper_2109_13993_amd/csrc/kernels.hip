@@ -478,8 +478,12 @@ __device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma
   double* __restrict__ H = d.H;
   double* __restrict__ eH = d.eH;
   __shared__ double sh[NT / 64];
-  const double* z = d.Z[buf] + (int64_t)blockIdx.x * d.ldz;
+  // the row is normalised here, once per iteration: d z is used for the
+  // entropy and, when the Gram refresh gave d != 1, stored back in place for
+  // the rest of the iteration
+  double* z = d.Z[buf] + (int64_t)blockIdx.x * d.ldz;
   const double dz = d.dsc[buf][blockIdx.x];
+  const bool store = dz != 1.0;
   const int W = NT >= 1024 && n >= ENT_WIDE_N ? 1024 : 256;
   double lc = 0.0, g = 0.0;
   if ((int)threadIdx.x < W) {
@@ -490,13 +494,21 @@ __device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma
         float flc = 0.f, fg = 0.f;
 #pragma unroll 4
         for (int c = 0; c < 32; ++c, k += W)
-          if (k < n) terms_mixed((float)(dz * z[k]), ca, cg, flc, fg);
+          if (k < n) {
+            const double zk = dz * z[k];
+            if (store) z[k] = zk;
+            terms_mixed((float)zk, ca, cg, flc, fg);
+          }
         lc += (double)flc * LN2;
         g += (double)fg;
       }
     } else {
 #pragma unroll 4
-      for (int64_t k = threadIdx.x; k < n; k += W) terms_f64(dz * z[k], lc, g);
+      for (int64_t k = threadIdx.x; k < n; k += W) {
+        const double zk = dz * z[k];
+        if (store) z[k] = zk;
+        terms_f64(zk, lc, g);
+      }
     }
   }
   lc = block_sum<NT>(lc, sh);
@@ -697,19 +709,15 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
   const int64_t k0 = (int64_t)chunk * a.chunk;
   const int64_t kend = min(n, k0 + (int64_t)a.chunk);
   const int nst = (int)((kend - k0 + PS - 1) / PS);
-  const double dv = mask ? dsc[v] : 0.0;
   const double* zrow = Z + (int64_t)(mask ? v : 0) * ldz;
-  // this thread's share of the staged target rows: fixed rows, so their
-  // scales are loaded once
-  // (a target position past the last variable, var >= r, is read from row
-  // r - 1 with scale 0, and its pairs are never kept)
-  double dB[NSTG];
+  // this thread's share of the staged target rows (a target position past
+  // the last variable, var >= r, is read from row r - 1, and its pairs are
+  // never kept)
   const double* srow[NSTG];
 #pragma unroll
   for (int i = 0; i < NSTG; ++i) {
     const int e = i * NT + (int)threadIdx.x;
     const int var = B * TB + e / (PS / 2);
-    dB[i] = var < r ? dsc[var] : 0.0;
     srow[i] = Z + (int64_t)min(var, r - 1) * ldz + 2 * (e % (PS / 2));
   }
   double2 stg[NSTG];
@@ -743,11 +751,12 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
     for (int i = 0; i < NSTG; ++i) {
       const int e = i * NT + (int)threadIdx.x;
       const int row = e / (PS / 2), c2 = e % (PS / 2);
-      *reinterpret_cast<double2*>(&buf[row][2 * c2]) = make_double2(stg[i].x * dB[i], stg[i].y * dB[i]);
+      // element-wise, so that stg stays in registers
+      *reinterpret_cast<double2*>(&buf[row][2 * c2]) = make_double2(stg[i].x, stg[i].y);
     }
     double zv[SPL];
 #pragma unroll
-    for (int i = 0; i < SPL; ++i) zv[i] = dv * zn[i];
+    for (int i = 0; i < SPL; ++i) zv[i] = zn[i];
     // buf is complete, and every wave has finished the stage that last used
     // the other buffer
     __syncthreads();
@@ -1300,7 +1309,7 @@ __device__ __forceinline__ void k_update_rows_body(const Dev& d, int t) {
   double* zo = Zn + (int64_t)wn * ldz;
 #pragma unroll 4
   for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
-    zo[k] = (dw * zw[k] - b * (dr * zr[k])) * sc;
+    zo[k] = (zw[k] - b * zr[k]) * sc;   // the rows are stored normalised
 }
 
 __global__ __launch_bounds__(256) void k_update_rows(const Dev* __restrict__ devs, const Dev one, int t) {

@@ -64,10 +64,13 @@ struct Dev {
   int band_adapt = 1;        // 1 = size later bands from the alive count, 0 = band_k0 blocks each
   int64_t ldz = 0;           // row stride of Z (doubles), multiple of 64
   double* Z[2] = {nullptr, nullptr};      // p x ldz normalised rows (ping-pong by iteration parity)
-  // Sig holds G, the covariance of the stored rows (ld = p), and dsc the row
-  // scales d_i = 1/sqrt(G_ii): the normalised rows are d_i z_i and their
-  // correlation is b_ij = G_ij d_i d_j.  Re-normalising lazily this way keeps the
-  // rank-1 recursion from amplifying rounding in the row variances.
+  // Sig holds G, the covariance of the rows the Gram was taken of (ld = p),
+  // and dsc the row scales d_i = 1/sqrt(G_ii): the normalised rows are d_i z_i
+  // and their correlation is b_ij = G_ij d_i d_j.  The entropy pass at the
+  // start of the iteration stores the rows as d_i z_i (in place), so every
+  // later kernel of the iteration reads normalised rows and uses d only for
+  // b.  Re-normalising from the Gram this way keeps the rank-1 recursion from
+  // amplifying rounding in the row variances.
   double* Sig[2] = {nullptr, nullptr};
   double* dsc[2] = {nullptr, nullptr};
   int32_t* idx[2] = {nullptr, nullptr};   // [p] compacted position -> original index
