@@ -38,16 +38,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("kernels.hip", "lingam_internal.h", "fp64_math.h")
+
+
+def kernel_source_digest():
+    """sha256 over the device sources, in a fixed order."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2109_13993_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per pair-kernel launch from the committed rocprofv3 counter
-    summary, or None if the kernel source changed since it was taken."""
-    import hashlib
+    summary, or None if the device sources changed since it was taken."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
-        src = open(os.path.join(ROOT, "paper_2109_13993_amd", "csrc", "kernels.hip"), "rb").read()
+        digest = kernel_source_digest()
     except OSError:
         return None
-    if hashlib.sha256(src).hexdigest() != rec.get("kernels_hip_sha256"):
+    if digest != rec.get("kernel_sources_sha256"):
         return None
     return rec.get("traffic_bytes_per_launch")
 
