@@ -87,7 +87,10 @@ def mixed_error_report(rm, r64, p):
     """Score error of the mixed run against the FP64 run over the iterations
     both share (same prefix of the order), the a-priori bounds, and the gap
     rule: iterations whose top score is separated from every other by the
-    bounds, and how many of those disagree with FP64 (must be 0)."""
+    bounds, and how many of those disagree with FP64 (must be 0).  A pruned
+    variable enters with its partial score, an upper bound on its T, so with
+    the threshold on the rule can only certify iterations whose pruned
+    variables sit far below the root."""
     import numpy as np
     diff = np.flatnonzero(rm.order != r64.order)
     upto = int(diff[0]) + 1 if diff.size else p - 1
@@ -260,6 +263,19 @@ def main():
         same = bool(np.array_equal(res64[-1].order, res_mix[-1].order))
         first_diff = int(np.argmax(res64[-1].order != res_mix[-1].order)) if not same else -1
         out["mixed_error"] = mixed_error_report(res_mix[-1], res64[-1], p)
+        # the gap rule on complete scores: one mixed search without the
+        # threshold, so that no competitor is known only by a partial score
+        rfull = lg.fit_order(X, precision="mixed", use_threshold=False)
+        full = mixed_error_report(rfull, res64[-1], p)
+        out["mixed_error"]["unpruned_search"] = {
+            "order_equals_threshold_search": bool(np.array_equal(rfull.order, res_mix[-1].order)),
+            "gap_rule_certified_iterations": full["gap_rule_certified_iterations"],
+            "gap_rule_violations": full["gap_rule_violations"],
+            "max_abs_dT": full["max_abs_dT"], "max_T_err_bound": full["max_T_err_bound"]}
+        log("mixed error: gap rule certifies %d iterations (threshold search), %d (unpruned search); "
+            "violations %d / %d" % (out["mixed_error"]["gap_rule_certified_iterations"],
+                                    full["gap_rule_certified_iterations"],
+                                    out["mixed_error"]["gap_rule_violations"], full["gap_rule_violations"]))
         out["fp64"] = {"value": v64, "ms_per_step": t64 * 1e3, "pair_kernel_ms_per_step": k64 * 1e3,
                        "pairs_evaluated": res64[-1].pairs_evaluated}
         out["speedup_fp32_vs_fp64"] = t64 / t_mix
