@@ -68,8 +68,8 @@ typedef struct lingam_opts {
   int32_t device;              /* HIP device ordinal; -1 = the current device */
   int32_t use_threshold;       /* 1 = threshold early exit (default), 0 = evaluate every pair */
   double gamma0;               /* > 0: initial threshold of every iteration; <= 0 (default):
-                                  adaptive, 1e-6 for the first iteration and then twice the
-                                  previous iteration's root score (any value gives the same
+                                  adaptive, 1e-6 for the first iteration and then 1.5 times
+                                  the previous iteration's root score (any value gives the same
                                   order; it only changes how many pairs are evaluated) */
   double gamma_mult;           /* threshold multiplier c; <= 1 selects 4 */
   int32_t cov_refresh_every;   /* k > 0: recompute the correlation matrix from the updated data

@@ -73,7 +73,7 @@ constexpr int SYNC_EVERY = 16;   // iterations queued between host checks
 constexpr int QUEUED_ROUNDS = 4; // threshold rounds queued per iteration
 constexpr int GRAM_SLICES_MAX = 16;  // sample slices of the split Gram
 constexpr int BAND_BLOCKS_DEFAULT = 1;  // target blocks of the first threshold band
-constexpr double GAMMA_ADAPT = 2.0;  // adaptive gamma0 = this x previous root score
+constexpr double GAMMA_ADAPT = 1.5;  // adaptive gamma0 = this x previous root score (by measurement)
 // Default Gram refresh period of the mixed mode: between refreshes the
 // paper's rank-1 UpdateCovMat carries the covariance; its drift over a few
 // iterations stays far below the binary32 rounding of the per-sample terms.
