@@ -228,6 +228,9 @@ Dev alloc_set(Allocs& al, int64_t n, int64_t p, const Plan& pl, const lingam_opt
   d.dsc[1] = al.get<double>(P);
   d.idx[0] = al.get<int32_t>(P);
   d.idx[1] = al.get<int32_t>(P);
+  d.ord[0] = al.get<int32_t>(P);
+  d.ord[1] = al.get<int32_t>(P);
+  d.perm = al.get<int32_t>(P);
   d.H = al.get<double>(P);
   d.eH = al.get<double>(P);
   d.eT = al.get<double>(P);
@@ -267,6 +270,7 @@ void init_set(const Dev& d, const lingam_opts& o, int limit, hipStream_t s, std:
     HIPCHK(hipMemcpyAsync(const_cast<int32_t*>(d.forced), o.forced_order, sizeof(int32_t) * o.forced_len,
                           hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(d.idx[0], iota.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d.ord[0], iota.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
   HIPCHK(launch_fill(d.Z[1], (int64_t)(P * d.ldz), 0.0, s));
   HIPCHK(launch_fill(d.M, (int64_t)pp, NAN, s));
   HIPCHK(launch_fill_u8(d.pend, (int64_t)pp, 0, s));
@@ -497,7 +501,7 @@ uint64_t lingam_workspace_size(int64_t n, int64_t p, const lingam_opts* o) {
   const uint64_t P = (uint64_t)p, pp = P * P;
   uint64_t b = 0;
   b += 2 * P * ldz * 8;                 // Z
-  b += 2 * pp * 8 + 2 * P * 4;          // Sigma, idx
+  b += 2 * pp * 8 + 5 * P * 4;          // Sigma, idx, ord, perm
   b += pp * 8 + pp;                     // M, pend
   b += (uint64_t)pl.nchunk * pp * 32;   // partials
   b += 4 * P * 8 + 2 * P;               // H, S, stats, alive/complete

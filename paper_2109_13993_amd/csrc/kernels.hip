@@ -689,10 +689,9 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
     double sj = 1.0;
     if (mask >> j & 1u) {
       const int w = B * TB + j0 + j;
-      // formed in ascending variable order, so a pair gets the same bits
-      // whichever of its variables is the row
-      const int lo = min(v, w), hi = max(v, w);
-      const double b = Sig[(int64_t)lo * p + hi] * dsc[lo] * dsc[hi];
+      // symmetric in v and w (Sigma is stored symmetric bit for bit), so a
+      // pair gets the same bits whichever of its variables is the row
+      const double b = Sig[(int64_t)v * p + w] * (dsc[v] * dsc[w]);
       const double om = 1.0 - b * b;
       if (!(om > DEGEN_EPS)) {
         if (lane == 0) raise_error(ctl, ST_DEGENERATE, idx[v], idx[w]);
@@ -939,11 +938,14 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
                              int round_end, int t, double gamma_mult, const int32_t* __restrict__ forced,
                              int forced_len, const int32_t* __restrict__ idx, Ctl* ctl) {
   __shared__ double sh_c[4], sh_i[4];
-  __shared__ int sh_ci[4], sh_pos[4], sh_cnt[4], sh_has[4];
+  __shared__ int sh_ci[4], sh_cix[4], sh_pos[4], sh_cnt[4], sh_has[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int want = t < forced_len ? forced[t] : -1;
   double minc = INFINITY, mini = INFINITY;
-  int ci = 0x7fffffff, pos = -1, has = 0;  // has: bit 0 some complete row, bit 1 some incomplete row
+  // ci: position of the smallest complete score, cix its original index
+  // (ties go to the lowest original index); has: bit 0 some complete row,
+  // bit 1 some incomplete row
+  int ci = 0x7fffffff, cix = 0x7fffffff, pos = -1, has = 0;
   // the scores of the first KC * 256 positions stay in registers for the
   // compaction below
   constexpr int KC = 8;
@@ -951,7 +953,8 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
   auto visit = [&](int y, double sy) {
     if (complete[y]) {
       has |= 1;
-      if (sy < minc || (sy == minc && y < ci)) { minc = sy; ci = y; }
+      const int iy = idx[y];
+      if (sy < minc || (sy == minc && iy < cix)) { minc = sy; ci = y; cix = iy; }
     } else {
       has |= 2;
       mini = fmin(mini, sy);
@@ -972,17 +975,19 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     const double oc = __shfl_xor(minc, off, 64);
-    const int oci = __shfl_xor(ci, off, 64);
-    if (oc < minc || (oc == minc && oci < ci)) { minc = oc; ci = oci; }
+    const int oci = __shfl_xor(ci, off, 64), ocix = __shfl_xor(cix, off, 64);
+    if (oc < minc || (oc == minc && ocix < cix)) { minc = oc; ci = oci; cix = ocix; }
     mini = fmin(mini, __shfl_xor(mini, off, 64));
     pos = max(pos, __shfl_xor(pos, off, 64));
     has |= __shfl_xor(has, off, 64);
   }
-  if (lane == 0) { sh_c[wv] = minc; sh_ci[wv] = ci; sh_i[wv] = mini; sh_pos[wv] = pos; sh_has[wv] = has; }
+  if (lane == 0) {
+    sh_c[wv] = minc; sh_ci[wv] = ci; sh_cix[wv] = cix; sh_i[wv] = mini; sh_pos[wv] = pos; sh_has[wv] = has;
+  }
   __syncthreads();
-  minc = sh_c[0]; ci = sh_ci[0]; mini = sh_i[0]; pos = sh_pos[0]; has = sh_has[0];
+  minc = sh_c[0]; ci = sh_ci[0]; cix = sh_cix[0]; mini = sh_i[0]; pos = sh_pos[0]; has = sh_has[0];
   for (int w = 1; w < 4; ++w) {
-    if (sh_c[w] < minc || (sh_c[w] == minc && sh_ci[w] < ci)) { minc = sh_c[w]; ci = sh_ci[w]; }
+    if (sh_c[w] < minc || (sh_c[w] == minc && sh_cix[w] < cix)) { minc = sh_c[w]; ci = sh_ci[w]; cix = sh_cix[w]; }
     mini = fmin(mini, sh_i[w]);
     pos = max(pos, sh_pos[w]);
     has |= sh_has[w];
@@ -1060,6 +1065,7 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
   double* __restrict__ S = d.S;
   uint8_t* __restrict__ complete = d.complete;
   const int32_t* alive_list = d.alive_list;
+  const int32_t* __restrict__ ord = d.ord[buf];
   const int nchunk = d.nchunk;
   const double n = (double)d.n;
   const int mixed = d.mixed;
@@ -1096,7 +1102,10 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
   double s = 0.0, es = 0.0;
   int incomplete = 0;
   const double hx = H[x];
-  for (int w = threadIdx.x; w < r; w += 256) {
+  // the row's tests in ascending original index of the other variable, so
+  // the score's bits do not depend on positions
+  for (int q = threadIdx.x; q < r; q += 256) {
+    const int w = ord[q];
     if (w == x) continue;
     // the flag, the stored test and its bound are fetched together; only a
     // pending test needs a second, dependent fetch (its chunk partials)
@@ -1288,6 +1297,74 @@ __device__ __forceinline__ void k_finish_iter_body(const Dev& d, int t) {
 // ============================================================================
 // a7: UpdateData and UpdateCovMat (Sec. 3.4), compacting out the root
 // ============================================================================
+// Positions of the survivors for the next iteration, once the root is
+// known: the new position of a variable is the rank of (S, original index)
+// among the remaining variables other than the root, so the next iteration
+// starts its threshold rounds with the variables that scored best in this
+// one.  Their rank by original index alone gives the next iteration's
+// canonical order (ord).  With more than RANK_MAX rows the positions keep
+// the original order (every earlier iteration had more rows, so they are
+// still in it).
+constexpr int RANK_MAX = 16384;
+constexpr int RANK_TILE = 1024;
+
+__device__ __forceinline__ void k_rank_body(const Dev& d, int t) {
+  const int r = rows_left(d, t);
+  const Ctl* ctl = d.ctl;
+  if (r < 2 || halted(ctl) || !ctl->done) return;
+  const int buf = t & 1;
+  const double* __restrict__ S = d.S;
+  const int32_t* __restrict__ idx = d.idx[buf];
+  int32_t* __restrict__ perm = d.perm;
+  int32_t* __restrict__ ordn = d.ord[buf ^ 1];
+  const int root = ctl->root;
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;  // old position
+  const bool mine = w < r && w != root;
+  if (r > RANK_MAX) {
+    if (mine) {
+      const int wn = w - (w > root ? 1 : 0);
+      perm[wn] = w;
+      ordn[wn] = wn;
+    }
+    return;
+  }
+  __shared__ double sh_s[RANK_TILE];
+  __shared__ int sh_i[RANK_TILE];
+  const double sw = mine ? S[w] : 0.0;
+  const int iw = mine ? idx[w] : 0;
+  int rs = 0, ri = 0;
+  for (int u0 = 0; u0 < r; u0 += RANK_TILE) {
+    const int cnt = min(RANK_TILE, r - u0);
+    __syncthreads();
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+      sh_s[k] = S[u0 + k];
+      sh_i[k] = idx[u0 + k];
+    }
+    __syncthreads();
+    if (mine) {
+      for (int k = 0; k < cnt; ++k) {
+        const int u = u0 + k;
+        if (u == root || u == w) continue;
+        const double su = sh_s[k];
+        const int iu = sh_i[k];
+        rs += (su < sw || (su == sw && iu < iw)) ? 1 : 0;
+        ri += iu < iw ? 1 : 0;
+      }
+    }
+  }
+  if (mine) {
+    perm[rs] = w;
+    ordn[ri] = rs;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rank(const Dev* __restrict__ devs, const Dev one, int t) {
+  if (devs)
+    k_rank_body(devs[blockIdx.z], t);
+  else
+    k_rank_body(one, t);
+}
+
 __device__ __forceinline__ void k_update_rows_body(const Dev& d, int t) {
   const int r = rows_left(d, t), p = d.p;
   const Ctl* ctl = d.ctl;
@@ -1300,7 +1377,7 @@ __device__ __forceinline__ void k_update_rows_body(const Dev& d, int t) {
   const double* __restrict__ dsc = d.dsc[buf];
   const int root = ctl->root;
   const int wn = blockIdx.y;                  // new position
-  const int w = wn + (wn >= root ? 1 : 0);    // old position
+  const int w = d.perm[wn];                   // old position
   const double dw = dsc[w], dr = dsc[root];
   const double b = Sig[(int64_t)w * p + root] * dw * dr;   // correlation of the normalised rows
   const double sc = 1.0 / sqrt(1.0 - b * b);
@@ -1338,22 +1415,23 @@ __device__ __forceinline__ void k_update_sigma_body(const Dev& d, int t, int rec
   const int rn = r - 1;
   const int64_t total = (int64_t)rn * rn;
   const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int32_t* __restrict__ perm = d.perm;
   if (gid < rn) {
-    const int w = (int)gid + ((int)gid >= root ? 1 : 0);
+    const int w = perm[gid];
     idxn[gid] = idx[w];
     if (recursion) dscn[gid] = 1.0;  // the recursion's rows are unit-variance by construction
   }
   if (!recursion) return;
   for (int64_t e = gid; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int an = (int)(e / rn), bn = (int)(e % rn);
-    const int a = an + (an >= root ? 1 : 0), b = bn + (bn >= root ? 1 : 0);
+    const int a = perm[an], b = perm[bn];
     double val;
     if (an == bn) {
       val = 1.0;
     } else {
       const double da = dsc[a], db = dsc[b], dr = dsc[root];
       const double ba = Sig[(int64_t)a * p + root] * da * dr, bb = Sig[(int64_t)b * p + root] * db * dr;
-      const double bab = Sig[(int64_t)a * p + b] * da * db;
+      const double bab = Sig[(int64_t)a * p + b] * (da * db);   // symmetric in a and b
       val = (bab - ba * bb) / (sqrt(1.0 - ba * ba) * sqrt(1.0 - bb * bb));
     }
     Sn[(int64_t)an * p + bn] = val;
@@ -1370,9 +1448,12 @@ __global__ __launch_bounds__(256) void k_update_sigma(const Dev* __restrict__ de
 hipError_t launch_iter_end(const Batch& b, int t, int refresh, hipStream_t s) {
   const int rn = b.p_max - t - 1;
   if (rn <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rank, dim3((rn + 1 + 255) / 256, 1, b.count), dim3(256), 0, s, DEVS(b), t);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const int xblocks = (int)std::min<int64_t>(16, (b.n_max + 255) / 256);
   hipLaunchKernelGGL(k_update_rows, dim3(xblocks, rn, b.count), dim3(256), 0, s, DEVS(b), t);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t total = std::max<int64_t>((int64_t)rn * rn, rn);
   int blocks = (int)std::min<int64_t>(std::max(8, 2048 / b.count), (total + 255) / 256);

@@ -73,7 +73,17 @@ struct Dev {
   // amplifying rounding in the row variances.
   double* Sig[2] = {nullptr, nullptr};
   double* dsc[2] = {nullptr, nullptr};
-  int32_t* idx[2] = {nullptr, nullptr};   // [p] compacted position -> original index
+  // Positions of the remaining variables.  After each root the survivors
+  // are placed in ascending order of their score in the finished iteration
+  // (ties by original index), so the next iteration's first target blocks
+  // hold the variables most likely to be causes, and its threshold prunes
+  // the other rows early.  Every result is formed in an order that does not
+  // depend on positions (scores sum their tests in ascending original
+  // index, ties go to the lowest original index), so positions change which
+  // pairs get evaluated, never a value.
+  int32_t* idx[2] = {nullptr, nullptr};   // [p] position -> original index
+  int32_t* ord[2] = {nullptr, nullptr};   // [p] rank by original index -> position
+  int32_t* perm = nullptr;                // [p] new position -> old position (set at each root)
   int mixed = 0;             // 1 = mixed-precision per-sample terms
   double* H = nullptr;       // [p] entropy estimate per compacted row
   double* eH = nullptr;      // [p] rounding bound of H (mixed mode; 0 in FP64 mode)
