@@ -84,8 +84,9 @@ typedef struct lingam_opts {
   int32_t band_blocks;         /* tuning: the threshold rounds compare every variable still below
                                   the threshold with bands of target blocks (8 variables each),
                                   refreshing the threshold state after each band.  0 (default): a
-                                  first band of 1 block, then bands sized from the number of
-                                  variables still below the threshold; k > 0: k blocks per band */
+                                  first band of 4 blocks (single MIXED search) or 1 block (FP64,
+                                  batches), then bands sized from the number of variables still
+                                  below the threshold; k > 0: k blocks per band */
   int32_t chunk_samples;       /* tuning: samples per work-group chunk (multiple of 256), 0 = auto */
   void* stream;                /* hipStream_t to run on; NULL = a library-owned stream */
   int32_t profile;             /* 1 = time every pair-kernel launch with HIP events on the
@@ -151,7 +152,11 @@ typedef struct lingam_dataset {
  * per set on the device), so many small searches share each launch; a set
  * whose iteration needs more threshold rounds than were queued leaves the
  * batch and is finished on its own.  The results are those of separate
- * lingam_fit_order calls with the same options, bit for bit.
+ * lingam_fit_order calls with the same options: the same order, and bit for
+ * bit the same T and T_err_bound entries wherever the score is complete in
+ * both.  (A batch may schedule its threshold bands differently from a
+ * single call, which changes only which variables end an iteration pruned,
+ * their partial scores and the pair counters.)
  *   sets[k].X: host or device memory per opts->x_on_device, with opts->x_dtype
  *     and opts->layout; a bootstrap set (sample_idx != NULL) needs a binary64
  *     p x n base, its sample_idx is host memory, n_idx samples are drawn.
