@@ -238,6 +238,7 @@ Dev alloc_set(Allocs& al, int64_t n, int64_t p, const Plan& pl, const lingam_opt
   d.ord[0] = al.get<int32_t>(P);
   d.ord[1] = al.get<int32_t>(P);
   d.perm = al.get<int32_t>(P);
+  d.Hp = al.get<double>(P * ENT_SEGS * 2);
   d.H = al.get<double>(P);
   d.eH = al.get<double>(P);
   d.eT = al.get<double>(P);
@@ -356,7 +357,10 @@ struct Fit {
     for (size_t k = 0; k < ps.size(); ++k) any_last |= (ps[k] - t == 1 && t < limits[k]);
     if (any_last) HIPCHK(launch_last(b, t, s));
     if (b.p_max - t < 2) return;
-    HIPCHK(launch_iter_start(b, t, threshold ? gamma0 : INFINITY, GAMMA_ADAPT, threshold ? 1 : 0, s));
+    // the previous iteration's row update summed the entropy terms unless a
+    // Gram refresh followed it
+    const int fused = t > 0 && !(refresh_every > 0 && t % refresh_every == 0) ? 1 : 0;
+    HIPCHK(launch_iter_start(b, t, threshold ? gamma0 : INFINITY, GAMMA_ADAPT, threshold ? 1 : 0, fused, s));
     queue_rounds(t);
     queue_tail(t);
   }
@@ -509,6 +513,7 @@ uint64_t lingam_workspace_size(int64_t n, int64_t p, const lingam_opts* o) {
   uint64_t b = 0;
   b += 2 * P * ldz * 8;                 // Z
   b += 2 * pp * 8 + 5 * P * 4;          // Sigma, idx, ord, perm
+  b += P * ENT_SEGS * 16;               // entropy sums of the updated rows
   b += pp * 8 + pp;                     // M, pend
   b += (uint64_t)pl.nchunk * pp * 32;   // partials
   b += 4 * P * 8 + 2 * P;               // H, S, stats, alive/complete

@@ -468,15 +468,39 @@ __device__ double block_sum(double x, double* sh) {
 // width, alone or in a batch.
 constexpr int64_t ENT_WIDE_N = 8192;
 
+// Sample segments of a row of n samples in the row update (at most
+// ENT_SEGS, at least 256 samples each).
+__host__ __device__ inline int entropy_segments_of(int64_t n) {
+  const int64_t s = (n + 255) / 256;
+  return (int)(s < ENT_SEGS ? s : ENT_SEGS);
+}
+int entropy_segments(int64_t n) { return entropy_segments_of(n); }
+
 template <bool MIXED, int NT>
-__device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma0, double adapt, int threshold) {
+__device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma0, double adapt, int threshold,
+                                               int fused) {
   const int r = rows_left(d, t);
   if ((int)blockIdx.x >= r || r < 2 || halted(d.ctl)) return;
   iter_init_row(d, t, (int)blockIdx.x, gamma0, adapt, threshold);
-  const int buf = t & 1;
   const int64_t n = d.n;
   double* __restrict__ H = d.H;
   double* __restrict__ eH = d.eH;
+  if (fused) {
+    // the row update summed the terms per segment: add them up in order
+    if (threadIdx.x == 0) {
+      const double* hp = d.Hp + (int64_t)blockIdx.x * ENT_SEGS * 2;
+      const int segs = entropy_segments_of(n);
+      double lc = 0.0, g = 0.0;
+      for (int q = 0; q < segs; ++q) {
+        lc += hp[2 * q];
+        g += hp[2 * q + 1];
+      }
+      H[blockIdx.x] = happ_from_sums(lc, g, (double)n);
+      eH[blockIdx.x] = MIXED ? happ_err_mixed(lc, g, (double)n) : 0.0;
+    }
+    return;
+  }
+  const int buf = t & 1;
   __shared__ double sh[NT / 64];
   // the row is normalised here, once per iteration: d z is used for the
   // entropy and, when the Gram refresh gave d != 1, stored back in place for
@@ -521,26 +545,31 @@ __device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma
 
 template <bool MIXED, int NT>
 __global__ __launch_bounds__(NT) void k_entropy(const Dev* __restrict__ devs, const Dev one, int t, double gamma0,
-                                                double adapt, int threshold) {
+                                                double adapt, int threshold, int fused) {
   if (devs)
-    k_entropy_body<MIXED, NT>(devs[blockIdx.z], t, gamma0, adapt, threshold);
+    k_entropy_body<MIXED, NT>(devs[blockIdx.z], t, gamma0, adapt, threshold, fused);
   else
-    k_entropy_body<MIXED, NT>(one, t, gamma0, adapt, threshold);
+    k_entropy_body<MIXED, NT>(one, t, gamma0, adapt, threshold, fused);
 }
 
-hipError_t launch_iter_start(const Batch& b, int t, double gamma0, double adapt, int threshold, hipStream_t s) {
+hipError_t launch_iter_start(const Batch& b, int t, double gamma0, double adapt, int threshold, int fused,
+                             hipStream_t s) {
   const int r = b.p_max - t;
   if (r < 2) return hipSuccess;
   const dim3 g(r, 1, b.count);
   const bool wide = b.n_max >= ENT_WIDE_N;
   if (b.mixed && wide)
-    hipLaunchKernelGGL((k_entropy<true, 1024>), g, dim3(1024), 0, s, DEVS(b), t, gamma0, adapt, threshold);
+    hipLaunchKernelGGL((k_entropy<true, 1024>), g, dim3(1024), 0, s, DEVS(b), t, gamma0, adapt, threshold,
+                       fused);
   else if (b.mixed)
-    hipLaunchKernelGGL((k_entropy<true, 256>), g, dim3(256), 0, s, DEVS(b), t, gamma0, adapt, threshold);
+    hipLaunchKernelGGL((k_entropy<true, 256>), g, dim3(256), 0, s, DEVS(b), t, gamma0, adapt, threshold,
+                       fused);
   else if (wide)
-    hipLaunchKernelGGL((k_entropy<false, 1024>), g, dim3(1024), 0, s, DEVS(b), t, gamma0, adapt, threshold);
+    hipLaunchKernelGGL((k_entropy<false, 1024>), g, dim3(1024), 0, s, DEVS(b), t, gamma0, adapt, threshold,
+                       fused);
   else
-    hipLaunchKernelGGL((k_entropy<false, 256>), g, dim3(256), 0, s, DEVS(b), t, gamma0, adapt, threshold);
+    hipLaunchKernelGGL((k_entropy<false, 256>), g, dim3(256), 0, s, DEVS(b), t, gamma0, adapt, threshold,
+                       fused);
   return hipGetLastError();
 }
 
@@ -1365,14 +1394,21 @@ __global__ __launch_bounds__(256) void k_rank(const Dev* __restrict__ devs, cons
     k_rank_body(one, t);
 }
 
-__device__ __forceinline__ void k_update_rows_body(const Dev& d, int t) {
+// UpdateData for one segment of one new row (blockIdx.y = new position,
+// blockIdx.x = segment).  With want_h (no Gram refresh before the next
+// iteration) it also sums the new row's entropy terms over its samples, in
+// the mode's precision (binary32 lane sums of at most 32 terms in the mixed
+// mode), for the next iteration's entropy.
+template <bool MIXED>
+__device__ __forceinline__ void k_update_rows_body(const Dev& d, int t, int want_h) {
   const int r = rows_left(d, t), p = d.p;
   const Ctl* ctl = d.ctl;
-  if (r < 2 || (int)blockIdx.y >= r - 1 || halted(ctl) || !ctl->done) return;
+  const int64_t ldz = d.ldz, n = d.n;
+  const int segs = entropy_segments_of(n);
+  if (r < 2 || (int)blockIdx.y >= r - 1 || (int)blockIdx.x >= segs || halted(ctl) || !ctl->done) return;
   const int buf = t & 1;
   const double* __restrict__ Z = d.Z[buf];
   double* __restrict__ Zn = d.Z[buf ^ 1];
-  const int64_t ldz = d.ldz, n = d.n;
   const double* __restrict__ Sig = d.Sig[buf];
   const double* __restrict__ dsc = d.dsc[buf];
   const int root = ctl->root;
@@ -1384,16 +1420,51 @@ __device__ __forceinline__ void k_update_rows_body(const Dev& d, int t) {
   const double* zr = Z + (int64_t)root * ldz;
   const double* zw = Z + (int64_t)w * ldz;
   double* zo = Zn + (int64_t)wn * ldz;
+  const int64_t step = (int64_t)segs * 256;
+  if (!want_h) {
 #pragma unroll 4
-  for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
-    zo[k] = (zw[k] - b * zr[k]) * sc;   // the rows are stored normalised
+    for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += step)
+      zo[k] = (zw[k] - b * zr[k]) * sc;   // the rows are stored normalised
+    return;
+  }
+  double lc = 0.0, g = 0.0;
+  int64_t k = blockIdx.x * 256 + threadIdx.x;
+  if constexpr (MIXED) {
+    const float ca = -2.0f * LOG2E_F, cg = -0.5f * LOG2E_F;
+    while (k < n) {
+      float flc = 0.f, fg = 0.f;
+      for (int c = 0; c < 32 && k < n; ++c, k += step) {
+        const double zk = (zw[k] - b * zr[k]) * sc;
+        zo[k] = zk;
+        terms_mixed((float)zk, ca, cg, flc, fg);
+      }
+      lc += (double)flc * LN2;
+      g += (double)fg;
+    }
+  } else {
+    for (; k < n; k += step) {
+      const double zk = (zw[k] - b * zr[k]) * sc;
+      zo[k] = zk;
+      terms_f64(zk, lc, g);
+    }
+  }
+  __shared__ double sh[4];
+  lc = block_sum256(lc, sh);
+  g = block_sum256(g, sh);
+  if (threadIdx.x == 0) {
+    double* hp = d.Hp + ((int64_t)wn * ENT_SEGS + blockIdx.x) * 2;
+    hp[0] = lc;
+    hp[1] = g;
+  }
 }
 
-__global__ __launch_bounds__(256) void k_update_rows(const Dev* __restrict__ devs, const Dev one, int t) {
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_update_rows(const Dev* __restrict__ devs, const Dev one, int t,
+                                                     int want_h) {
   if (devs)
-    k_update_rows_body(devs[blockIdx.z], t);
+    k_update_rows_body<MIXED>(devs[blockIdx.z], t, want_h);
   else
-    k_update_rows_body(one, t);
+    k_update_rows_body<MIXED>(one, t, want_h);
 }
 
 // Work-group 0 first records the iteration's results (or halts an iteration
@@ -1451,8 +1522,12 @@ hipError_t launch_iter_end(const Batch& b, int t, int refresh, hipStream_t s) {
   hipLaunchKernelGGL(k_rank, dim3((rn + 1 + 255) / 256, 1, b.count), dim3(256), 0, s, DEVS(b), t);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int xblocks = (int)std::min<int64_t>(16, (b.n_max + 255) / 256);
-  hipLaunchKernelGGL(k_update_rows, dim3(xblocks, rn, b.count), dim3(256), 0, s, DEVS(b), t);
+  const int xblocks = entropy_segments_of(b.n_max);
+  const int want_h = refresh ? 0 : 1;
+  if (b.mixed)
+    hipLaunchKernelGGL(k_update_rows<true>, dim3(xblocks, rn, b.count), dim3(256), 0, s, DEVS(b), t, want_h);
+  else
+    hipLaunchKernelGGL(k_update_rows<false>, dim3(xblocks, rn, b.count), dim3(256), 0, s, DEVS(b), t, want_h);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t total = std::max<int64_t>((int64_t)rn * rn, rn);

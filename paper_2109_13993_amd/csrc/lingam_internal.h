@@ -20,6 +20,10 @@ constexpr int CHUNK_MAX_MIXED = 2048;
 // Degeneracy guard on 1 - corr^2 of an evaluated pair (and row variance).
 constexpr double DEGEN_EPS = 1e-12;
 constexpr int PAIR_SLOTS = 2048;
+// Sample segments of a row in the row update (one work-group each); with no
+// Gram refresh between two iterations the update also sums the new row's
+// entropy terms per segment, and the next iteration only adds them up.
+constexpr int ENT_SEGS = 16;
 
 enum Status : int32_t { ST_OK = 0, ST_INVALID = 1, ST_NONFINITE = 2, ST_DEGENERATE = 3 };
 
@@ -84,6 +88,7 @@ struct Dev {
   int32_t* idx[2] = {nullptr, nullptr};   // [p] position -> original index
   int32_t* ord[2] = {nullptr, nullptr};   // [p] rank by original index -> position
   int32_t* perm = nullptr;                // [p] new position -> old position (set at each root)
+  double* Hp = nullptr;      // [p][ENT_SEGS][2] entropy sums of the updated rows, per segment
   int mixed = 0;             // 1 = mixed-precision per-sample terms
   double* H = nullptr;       // [p] entropy estimate per compacted row
   double* eH = nullptr;      // [p] rounding bound of H (mixed mode; 0 in FP64 mode)
@@ -154,7 +159,10 @@ hipError_t launch_standardize(const Batch& b, hipStream_t s);
 hipError_t launch_gram(const Batch& b, int buf, int t, hipStream_t s);
 // Start of iteration t: the entropies of the remaining rows and the
 // iteration's set-up (tests not evaluated, scores 0, threshold state).
-hipError_t launch_iter_start(const Batch& b, int t, double gamma0, double adapt, int threshold, hipStream_t s);
+// fused: the row update of iteration t - 1 left the entropy sums (no Gram
+// refresh in between), so only their segments are added up.
+hipError_t launch_iter_start(const Batch& b, int t, double gamma0, double adapt, int threshold, int fused,
+                             hipStream_t s);
 // Shape of the later (bounded) pair-kernel bands of a launch over b: rows
 // per work-group and the work-groups one data set gets.
 void pair_band_shape(const Batch& b, int& rows_per_group, int& groups);
@@ -170,6 +178,7 @@ hipError_t launch_record_M(const Batch& b, int t, hipStream_t s);
 // iteration halts instead), UpdateData and UpdateCovMat, and with refresh
 // the Gram of the updated rows.
 hipError_t launch_iter_end(const Batch& b, int t, int refresh, hipStream_t s);
+int entropy_segments(int64_t n);
 hipError_t launch_last(const Batch& b, int t, hipStream_t s);
 hipError_t launch_resume(const Batch& b, hipStream_t s);
 hipError_t launch_gather(const double* X, int64_t n_src, int64_t p, const int64_t* idx, int64_t n_idx,
