@@ -75,7 +75,7 @@ typedef struct lingam_opts {
   int32_t cov_refresh_every;   /* k > 0: recompute the correlation matrix from the updated data
                                   every k iterations (FP64 matrix cores), the rank-1 UpdateCovMat
                                   recursion in between; 0 = the recursion only; < 0 (default): 1
-                                  in FP64 mode, 8 in MIXED mode */
+                                  in FP64 mode, 16 in MIXED mode */
   int32_t max_roots;           /* 0 = full order; m > 0 = stop after m roots */
   const int32_t* forced_order; /* optional host array: follow these roots for the first
                                   forced_len iterations (scores are still computed) */

@@ -83,7 +83,7 @@ constexpr double GAMMA_ADAPT = 1.5;  // adaptive gamma0 = this x previous root s
 // Default Gram refresh period of the mixed mode: between refreshes the
 // paper's rank-1 UpdateCovMat carries the covariance; its drift over a few
 // iterations stays far below the binary32 rounding of the per-sample terms.
-constexpr int REFRESH_MIXED = 8;
+constexpr int REFRESH_MIXED = 16;
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
