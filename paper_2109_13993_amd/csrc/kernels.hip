@@ -1336,6 +1336,8 @@ __device__ __forceinline__ void k_finish_iter_body(const Dev& d, int t) {
 // still in it).
 constexpr int RANK_MAX = 16384;
 constexpr int RANK_TILE = 1024;
+constexpr int RANK_SPLIT = 8;                 // threads per row, each counting a share of the others
+constexpr int RANK_ROWS = 256 / RANK_SPLIT;   // rows per work-group
 
 __device__ __forceinline__ void k_rank_body(const Dev& d, int t) {
   const int r = rows_left(d, t);
@@ -1347,10 +1349,11 @@ __device__ __forceinline__ void k_rank_body(const Dev& d, int t) {
   int32_t* __restrict__ perm = d.perm;
   int32_t* __restrict__ ordn = d.ord[buf ^ 1];
   const int root = ctl->root;
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;  // old position
+  const int sub = threadIdx.x % RANK_SPLIT;
+  const int w = blockIdx.x * RANK_ROWS + threadIdx.x / RANK_SPLIT;  // old position
   const bool mine = w < r && w != root;
   if (r > RANK_MAX) {
-    if (mine) {
+    if (mine && sub == 0) {
       const int wn = w - (w > root ? 1 : 0);
       perm[wn] = w;
       ordn[wn] = wn;
@@ -1371,7 +1374,7 @@ __device__ __forceinline__ void k_rank_body(const Dev& d, int t) {
     }
     __syncthreads();
     if (mine) {
-      for (int k = 0; k < cnt; ++k) {
+      for (int k = sub; k < cnt; k += RANK_SPLIT) {
         const int u = u0 + k;
         if (u == root || u == w) continue;
         const double su = sh_s[k];
@@ -1381,7 +1384,13 @@ __device__ __forceinline__ void k_rank_body(const Dev& d, int t) {
       }
     }
   }
-  if (mine) {
+  // the RANK_SPLIT threads of a row are consecutive lanes of one wave
+#pragma unroll
+  for (int m = 1; m < RANK_SPLIT; m <<= 1) {
+    rs += __shfl_xor(rs, m, 64);
+    ri += __shfl_xor(ri, m, 64);
+  }
+  if (mine && sub == 0) {
     perm[rs] = w;
     ordn[ri] = rs;
   }
@@ -1519,7 +1528,7 @@ __global__ __launch_bounds__(256) void k_update_sigma(const Dev* __restrict__ de
 hipError_t launch_iter_end(const Batch& b, int t, int refresh, hipStream_t s) {
   const int rn = b.p_max - t - 1;
   if (rn <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rank, dim3((rn + 1 + 255) / 256, 1, b.count), dim3(256), 0, s, DEVS(b), t);
+  hipLaunchKernelGGL(k_rank, dim3((rn + 1 + RANK_ROWS - 1) / RANK_ROWS, 1, b.count), dim3(256), 0, s, DEVS(b), t);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int xblocks = entropy_segments_of(b.n_max);
