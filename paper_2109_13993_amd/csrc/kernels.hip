@@ -958,7 +958,7 @@ hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense,
 // threads: the termination test, the threshold update of a round that ended
 // without a root, the root, the next band's threshold state and the
 // compacted alive list.  One pass over the scores gives the smallest
-// complete score (with its lowest position) and the smallest incomplete one;
+// complete score (with its lowest original index) and the smallest incomplete one;
 // for a threshold gamma, some complete score is <= gamma iff the first is,
 // and some incomplete one iff the second is, so the threshold loop needs no
 // further pass.
