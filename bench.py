@@ -10,7 +10,8 @@ selection + rank-1 update) on the input already resident in device memory.
 Reported: evaluated pair-samples per second of the mixed-precision path
 (binary32 per-sample terms) and its order wall time, the same for the FP64
 path, the pair kernel's VALU roofline fraction (pair-kernel time measured with
-HIP events on the library's stream), and the FP64 CPU oracle's rate on a
+HIP events attached to each pair-kernel launch on the library's stream), and
+the FP64 CPU oracle's rate on a
 bounded sample of the same workload.  Prints one JSON line on stdout.
 """
 import argparse
@@ -65,9 +66,10 @@ def measured_traffic():
 
 def timed_runs(lg, X, precision, steps, warmup, **kw):
     """Wall time per search over `steps` searches (after `warmup`), then the
-    same number of searches again with every pair-kernel launch bracketed by
-    HIP events on the library's stream (the event records add a little time,
-    so those searches give the kernel durations, not the wall time)."""
+    same number of searches again with a pair of HIP events attached to every
+    pair-kernel launch on the library's stream, which take the launch's own
+    start and end (timed launches slow the search as a whole, so those
+    searches give the kernel durations, not the wall time)."""
     import torch
     for _ in range(warmup):
         lg.fit_order(X, precision=precision, **kw)
