@@ -468,11 +468,12 @@ __device__ double block_sum(double x, double* sh) {
 // width, alone or in a batch.
 constexpr int64_t ENT_WIDE_N = 8192;
 
-// Sample segments of a row of n samples in the row update (at most
-// ENT_SEGS, at least 256 samples each).
+// Sample segments of a row of n samples in the row update: at most
+// ENT_SEGS, and about 1024 samples or more each (4 per thread), so that
+// short rows do not spread over many nearly empty work-groups.
 __host__ __device__ inline int entropy_segments_of(int64_t n) {
-  const int64_t s = (n + 255) / 256;
-  return (int)(s < ENT_SEGS ? s : ENT_SEGS);
+  const int64_t s = (n + 1023) / 1024;
+  return (int)(s < 1 ? 1 : (s < ENT_SEGS ? s : ENT_SEGS));
 }
 int entropy_segments(int64_t n) { return entropy_segments_of(n); }
 
