@@ -475,7 +475,6 @@ __host__ __device__ inline int entropy_segments_of(int64_t n) {
   const int64_t s = (n + 1023) / 1024;
   return (int)(s < 1 ? 1 : (s < ENT_SEGS ? s : ENT_SEGS));
 }
-int entropy_segments(int64_t n) { return entropy_segments_of(n); }
 
 template <bool MIXED, int NT>
 __device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma0, double adapt, int threshold,

@@ -178,7 +178,6 @@ hipError_t launch_record_M(const Batch& b, int t, hipStream_t s);
 // iteration halts instead), UpdateData and UpdateCovMat, and with refresh
 // the Gram of the updated rows.
 hipError_t launch_iter_end(const Batch& b, int t, int refresh, hipStream_t s);
-int entropy_segments(int64_t n);
 hipError_t launch_last(const Batch& b, int t, hipStream_t s);
 hipError_t launch_resume(const Batch& b, hipStream_t s);
 hipError_t launch_gather(const double* X, int64_t n_src, int64_t p, const int64_t* idx, int64_t n_idx,
