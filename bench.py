@@ -43,11 +43,17 @@ KERNEL_SOURCES = ("kernels.hip", "lingam_internal.h", "fp64_math.h")
 
 
 def kernel_source_digest():
-    """sha256 over the device sources, in a fixed order."""
+    """sha256 over the code of the device sources, in a fixed order: comments
+    are dropped and white space collapsed, so only a change of the code
+    itself invalidates the recorded traffic."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2109_13993_amd", "csrc", name), "rb").read())
+        text = open(os.path.join(ROOT, "paper_2109_13993_amd", "csrc", name)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -21,9 +21,13 @@
 //                  S_i = sum_j min(0, I_ij)^2 and the threshold state; its last
 //                  work-group applies the termination test and the threshold
 //                  update of the Scheduler (Alg. 6 / Sec. 4.3) and picks the root.
+//   k_rank         Positions of the survivors for the next iteration, in order
+//                  of their score in this one.
 //   k_update_*     UpdateData and UpdateCovMat (Sec. 3.4): rank-1 update of the
-//                  remaining rows and of Sigma, compacting out the root; the
-//                  iteration's results are recorded first.
+//                  remaining rows and of Sigma into their new positions (the
+//                  row update also sums the next iteration's entropy terms
+//                  when no Gram refresh follows); the iteration's results are
+//                  recorded first.
 #include "lingam_internal.h"
 #include "fp64_math.h"
 
