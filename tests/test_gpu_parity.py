@@ -237,6 +237,36 @@ def test_largest_config_first_roots():
     _log("p=1000 n=50000 mixed: full order in %.2f s, %d pairs evaluated" % (gm.seconds_total, gm.pairs_evaluated))
 
 
+def test_many_variables_first_roots():
+    # p=2100: more rows than the decision keeps in registers (2048) and than
+    # one tile of the rank kernel (1024), so both take their long paths.  The
+    # first 4 roots of the FP64 search are checked against the oracle at
+    # their iterations (the root and 5 sampled variables, with the GPU's root
+    # prefix), and the mixed search must give the same first roots.
+    ds = synth.lingam_dataset(2100, 2000, 0.005, "uniform", rng=np.random.default_rng(21))
+    X = ds.X
+    p = X.shape[0]
+    g = lg.fit_order(X, precision="fp64", max_roots=4)
+    rng = np.random.default_rng(22)
+    for t in range(4):
+        prefix = [int(v) for v in g.order[:t]]
+        root = int(g.order[t])
+        rest = sorted(set(range(p)) - set(prefix) - {root})
+        vars_ = sorted([root] + rng.choice(rest, 5, replace=False).tolist())
+        T, _ = oracle.sampled_at(X, prefix, t, vars=vars_, pairs=[])
+        T = np.asarray(T)
+        got = g.T[t, vars_]
+        fin = g.T_state[t, vars_] == 1
+        rel = np.abs(got[fin] - T[fin]) / np.maximum(np.abs(T[fin]), 1e-12)
+        _log("p=2100 t=%d root %d: max rel |dT| %.2e" % (t, root, rel.max() if rel.size else 0.0))
+        assert fin[vars_.index(root)]
+        assert rel.size == 0 or rel.max() < 1e-8
+        others = np.delete(T, vars_.index(root))
+        assert np.all(T[vars_.index(root)] >= others - 1e-8 * np.abs(others) - 1e-15)
+    gm = lg.fit_order(X, precision="mixed", max_roots=4)
+    assert list(gm.order[:4]) == list(g.order[:4])
+
+
 def test_fullsize_runs_are_deterministic_and_threshold_exact(cfg3):
     X = cfg3.X
     a = lg.fit_order(X, precision="mixed")
