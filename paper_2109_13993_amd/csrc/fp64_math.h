@@ -27,10 +27,13 @@
 
 namespace lingam {
 
-// Every product-sum below is an explicit fused multiply-add and nothing else
-// is contracted, so a host build performs the same binary64 operations in
-// the same order as the device build.
-__host__ __device__ inline double log1p_unit(double y) {
+// log1p_unit_with(y, rcp) takes the reciprocal estimate as a parameter (the
+// host test runs it with deliberately perturbed ones); log1p_unit uses the
+// hardware estimate on the device and a division on the host.  Every
+// product-sum is an explicit fused multiply-add and nothing else is
+// contracted, so both builds perform the same operations in the same order.
+template <class Rcp>
+__host__ __device__ inline double log1p_unit_with(double y, Rcp rcp) {
 #if defined(__clang__)
 #pragma clang fp contract(off)
 #endif
@@ -39,7 +42,14 @@ __host__ __device__ inline double log1p_unit(double y) {
   const bool hi = z > 1.4142135623730951;
   const double m = hi ? 0.5 * z : z;   // exact
   const double f = m - 1.0;            // exact (m within a factor 2 of 1)
-  const double s = f / (2.0 + f);
+  // s = f / (2 + f) from a reciprocal estimate r0 of relative error e0 and
+  // two Newton steps on the quotient, each multiplying its relative error
+  // by e0: 2^-24 (the hardware estimate on this range) -> 2^-48 -> 2^-72
+  const double dd = 2.0 + f;           // exact
+  const double r0 = rcp(dd);
+  double s = f * r0;
+  s = std::fma(r0, std::fma(-s, dd, f), s);
+  s = std::fma(r0, std::fma(-s, dd, f), s);
   const double w = s * s;
   // q = 2/3 + 2/5 w + ... + 2/19 w^8, Horner from the highest power
   double q = 2.0 / 19.0;
@@ -61,5 +71,17 @@ __host__ __device__ inline double log1p_unit(double y) {
   const double corr = c * std::fma(-0.5, z, 1.5);
   return (hi ? lm + 0.6931471805599453 : lm) + corr;
 }
+
+struct RcpEstimate {
+  __host__ __device__ double operator()(double x) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcp(x);    // v_rcp_f64
+#else
+    return 1.0 / x;
+#endif
+  }
+};
+
+__host__ __device__ inline double log1p_unit(double y) { return log1p_unit_with(y, RcpEstimate{}); }
 
 }  // namespace lingam

@@ -1,6 +1,9 @@
 // Host check of log1p_unit (the binary64 log(1 + y), 0 <= y <= 1, of the
 // FP64 path) against a long double reference: prints the largest error in
-// units in the last place over a sweep of the range.
+// units in the last place over a sweep of the range, for the host's exact
+// reciprocal and for reciprocal estimates off by 2^-23 relative either way
+// (twice the largest error measured for the device's v_rcp_f64 estimate on
+// the range the function uses).
 #include "fp64_math.h"
 
 #include <cfloat>
@@ -11,18 +14,22 @@
 int main() {
   double max_ulp = 0.0, worst = 0.0;
   long bad = 0;
+  const double skew[3] = {0.0, std::ldexp(1.0, -23), -std::ldexp(1.0, -23)};
   auto check = [&](double y) {
     const long double ref = log1pl((long double)y);
-    const double got = lingam::log1p_unit(y);
-    if (ref == 0.0L) {
-      if (got != 0.0) ++bad;
-      return;
-    }
-    const double ulp = std::ldexp(1.0, std::ilogb((double)ref) - 52);
-    const double e = (double)fabsl((long double)got - ref) / ulp;
-    if (!(e <= max_ulp)) {
-      max_ulp = e;
-      worst = y;
+    for (double e : skew) {
+      const double got = e == 0.0 ? lingam::log1p_unit(y)
+                                  : lingam::log1p_unit_with(y, [e](double x) { return (1.0 / x) * (1.0 + e); });
+      if (ref == 0.0L) {
+        if (got != 0.0) ++bad;
+        continue;
+      }
+      const double ulp = std::ldexp(1.0, std::ilogb((double)ref) - 52);
+      const double err = (double)fabsl((long double)got - ref) / ulp;
+      if (!(err <= max_ulp)) {
+        max_ulp = err;
+        worst = y;
+      }
     }
   };
   std::mt19937_64 g(20210928);
