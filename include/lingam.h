@@ -46,14 +46,27 @@ typedef enum lingam_status {
   LINGAM_E_UNSUPPORTED = 6  /* option combination not supported */
 } lingam_status;
 
-/* Arithmetic of the per-sample entropy reductions (the hot path).
+/* Arithmetic of the per-sample entropy reductions (the hot path), and of
+ * the stored rows (Sec. 3.4 keeps the normalised data and its covariance).
  *   FP64 : everything in binary64.
  *   MIXED: the per-sample log cosh / exp terms in binary32 on the hardware
  *          exp2/log2 units, summed in binary32 over at most 32 samples per lane
  *          and then in binary64; residuals are formed in binary64 and then
  *          rounded; normalisation, covariance, regression coefficients,
- *          rank-1 updates and score sums stay binary64. */
-typedef enum lingam_precision { LINGAM_PREC_FP64 = 0, LINGAM_PREC_MIXED = 1 } lingam_precision;
+ *          rank-1 updates and score sums stay binary64.
+ *   FP32_STORAGE: MIXED with the normalised rows stored in binary32 (half the
+ *          memory and traffic): residuals are formed by binary32 fused
+ *          multiply-adds from the stored rows and b rounded to binary32; the
+ *          covariance (of the stored rows), b, 1/sqrt(1 - b^2), the rank-1
+ *          updates (rounded once when stored) and the score sums stay binary64.
+ *          T_err_bound adds the residuals' input error.  Each iteration's rows
+ *          are re-rounded, so the data drift from the binary64 path by about
+ *          u32 per update; the bound covers one iteration on its stored rows. */
+typedef enum lingam_precision {
+  LINGAM_PREC_FP64 = 0,
+  LINGAM_PREC_MIXED = 1,
+  LINGAM_PREC_FP32_STORAGE = 2
+} lingam_precision;
 
 /* Layout of X.  VAR_MAJOR is the paper's p x n matrix, row i = the n samples
  * of variable i (Alg. 1 input).  SAMPLE_MAJOR is n x p, row k = sample k. */
@@ -75,7 +88,7 @@ typedef struct lingam_opts {
   int32_t cov_refresh_every;   /* k > 0: recompute the correlation matrix from the updated data
                                   every k iterations (FP64 matrix cores), the rank-1 UpdateCovMat
                                   recursion in between; 0 = the recursion only; < 0 (default): 1
-                                  in FP64 mode, 16 in MIXED mode */
+                                  in FP64 mode, 16 in MIXED and FP32_STORAGE modes */
   int32_t max_roots;           /* 0 = full order; m > 0 = stop after m roots */
   const int32_t* forced_order; /* optional host array: follow these roots for the first
                                   forced_len iterations (scores are still computed) */
@@ -91,6 +104,31 @@ typedef struct lingam_opts {
   void* stream;                /* hipStream_t to run on; NULL = a library-owned stream */
   int32_t profile;             /* 1 = time every pair-kernel launch with HIP events on the
                                   stream (fills seconds_pair_kernel / pair_kernel_launches) */
+  void* workspace;             /* optional caller-owned device memory on `device` (e.g. from the
+                                  PyTorch allocator), 256-byte aligned, that the call carves every
+                                  device buffer from instead of allocating; NULL (default) = one
+                                  allocation of the library per call.  It must hold at least
+                                  lingam_workspace_size() (lingam_workspace_size_batch() for a
+                                  batch) bytes, else the call returns LINGAM_E_NOMEM before any
+                                  device work.  Not retained after the call returns; calls that
+                                  share one workspace must not overlap. */
+  uint64_t workspace_bytes;    /* size of `workspace` in bytes */
+  int32_t estimate_B;          /* 1 = after the order, estimate the causal strengths B into
+                                  result.B (Alg. 1, last step); needs the full order
+                                  (max_roots 0) and p <= 8000 */
+  int32_t batch_queue;         /* batches: 1 (default) = the pair and score work of every data set
+                                  on one device work queue served by a persistent grid (finished
+                                  or small sets occupy no work-groups); 0 = one grid slice per set */
+  int32_t graph;               /* batches: 1 = capture each window of 16 iterations into a HIP graph
+                                  and replay it; instantiated graphs are kept for later calls with
+                                  device memory at the same address and of the same layout (pass the
+                                  same opts.workspace).  0 (default) = launch kernel by kernel */
+  double band_target;          /* tuning: pair-samples (alive rows x targets x n) that a later
+                                  threshold band of round 0 aims at; <= 0 (default) = 6e7 for a single
+                                  MIXED / FP32_STORAGE search, 2e7 otherwise */
+  int32_t first_band_blocks;   /* tuning: target blocks of an iteration's first threshold band, the
+                                  later bands sized as by default (band_blocks = 0); 0 (default) = 4
+                                  for a single MIXED / FP32_STORAGE search, 1 otherwise */
 } lingam_opts;
 
 /* Outputs.  All arrays are host memory owned by the caller; NULL = not wanted. */
@@ -108,6 +146,10 @@ typedef struct lingam_result {
                            exp2/log2, lane sums), given the same data; 0 in FP64 mode, NaN
                            where T is NaN.  When the two largest T of an iteration differ by
                            more than the sum of their bounds, the root is the exact one. */
+  double* B;            /* [p*p] with opts.estimate_B: B[i*p + j] = causal strength of x_j on
+                           x_i, the least-squares coefficient of x_j when x_i is regressed
+                           (with an intercept) on every variable before it in the order; 0
+                           where x_j does not precede x_i */
   uint64_t pairs_evaluated;   /* unordered pairs whose test was needed and evaluated */
   uint64_t pair_samples;      /* pairs_evaluated x n (the throughput unit) */
   uint64_t pairs_computed;    /* pairs actually run by the kernel (>= pairs_evaluated) */
@@ -167,8 +209,33 @@ typedef struct lingam_dataset {
 lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets,
                                      const lingam_opts* o, lingam_result* outs);
 
-/* Device bytes the library allocates for one call of lingam_fit_order. */
+/* The same for one call of lingam_fit_order_batch over these data sets
+ * (0 if the batch is invalid). */
+uint64_t lingam_workspace_size_batch(int32_t count, const lingam_dataset* sets, const lingam_opts* o);
+
+/* Device bytes one call of lingam_fit_order with these shape and options
+ * uses (the workspace it allocates, or the least opts->workspace_bytes it
+ * accepts); 0 for an invalid shape.  It depends on n, p, precision,
+ * x_on_device, x_dtype, record_M_iters, forced_len and chunk_samples. */
 uint64_t lingam_workspace_size(int64_t n, int64_t p, const lingam_opts* o);
+
+
+/*
+ * Alg. 1, last step: the causal strengths B of X from a given causal order
+ * (Sec. 2.3: covariance-based least-squares regressions along the order).
+ * Each variable is regressed, with an intercept, on every variable before
+ * it in `order`; all regressions come from one binary64 Cholesky
+ * factorisation of the input's correlation matrix permuted into the order.
+ *   X     : as for lingam_fit_order (host or device, layout, dtype per opts)
+ *   order : [p] host array, a permutation of 0..p-1 (roots first)
+ *   B     : [p*p] host array, caller-owned: B[i*p + j] = coefficient of x_j in
+ *           the regression of x_i, 0 where x_j does not precede x_i.
+ * opts->precision chooses the stored rows the correlation is formed from
+ * (binary32 rows for FP32_STORAGE); the factorisation is binary64 always.
+ * Returns INVALID for a bad order or p > 8000, DEGENERATE (bad_i unset) if a
+ * variable is a linear function of those before it. */
+lingam_status lingam_estimate_B(const void* X, int64_t n, int64_t p, const int32_t* order,
+                                const lingam_opts* o, double* B);
 
 /* Static text for a status code. */
 const char* lingam_status_string(lingam_status s);

@@ -198,9 +198,16 @@ int oracle_compare(const double* xi, const double* xj, int64_t n, double* I_out)
  *   only : optional [r] mask; when given, only rows with only[a] != 0 get
  *          scores (other S entries are NaN) -- used by sampled checks.
  * On a degenerate pair, bad_a and bad_b receive the positions in U. */
+static int find_root_scores_once(const double* Z, int64_t n, const int32_t* U, int32_t r,
+                                 const double* H, double* S, double* Mrow, double* Brow,
+                                 int nthreads, int32_t* bad_a, int32_t* bad_b);
+
 static int find_root_scores(const double* Z, int64_t n, const int32_t* U, int32_t r,
                             const double* H, double* S, double* Mrow, double* Brow,
-                            const uint8_t* only, int nthreads, int32_t* bad_a, int32_t* bad_b) {
+                            const uint8_t* only, int nthreads, int32_t* bad_a, int32_t* bad_b,
+                            int pair_once) {
+  if (pair_once && !only)
+    return find_root_scores_once(Z, n, U, r, H, S, Mrow, Brow, nthreads, bad_a, bad_b);
   int status = OR_OK;
   int32_t ba = -1, bb = -1;
 #ifdef _OPENMP
@@ -250,6 +257,81 @@ static int find_root_scores(const double* Z, int64_t n, const int32_t* U, int32_
     }
     free(scratch);
   }
+  if (bad_a) *bad_a = ba;
+  if (bad_b) *bad_b = bb;
+  return status;
+}
+
+/* The same scores with each unordered pair evaluated once (messaging,
+ * Sec. 3.1): Compare of (b, a) evaluates the two residual entropies of
+ * Compare of (a, b) with the roles swapped, and the grouping of Eq. (Itest)
+ * makes its result the exact IEEE negation, so I_ba is taken as -I_ab.  The
+ * scores are then summed exactly as above (ascending b), so every output is
+ * bitwise the one of the ordered evaluation; only the work halves. */
+static int find_root_scores_once(const double* Z, int64_t n, const int32_t* U, int32_t r,
+                                 const double* H, double* S, double* Mrow, double* Brow,
+                                 int nthreads, int32_t* bad_a, int32_t* bad_b) {
+  int status = OR_OK;
+  int32_t ba = -1, bb = -1;
+  double* Mall = (double*)malloc(sizeof(double) * (size_t)r * (size_t)r);
+  double* Ball = Brow ? (double*)malloc(sizeof(double) * (size_t)r * (size_t)r) : NULL;
+  if (!Mall || (Brow && !Ball)) {
+    free(Mall); free(Ball);
+    return OR_E_NOMEM;
+  }
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads)
+#endif
+  {
+    double* scratch = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    if (!scratch) {
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+      status = OR_E_NOMEM;
+    }
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+    for (int32_t a = 0; a < r; ++a) {
+      if (!scratch) continue;
+      const double* zi = Z + (int64_t)U[a] * n;
+      Mall[(int64_t)a * r + a] = NAN;
+      if (Ball) Ball[(int64_t)a * r + a] = NAN;
+      for (int32_t b = a + 1; b < r; ++b) {
+        const double* zj = Z + (int64_t)U[b] * n;
+        double I = NAN, corr = NAN;
+        int st = compare_normalized(zi, zj, H[a], H[b], n, scratch, &I, Ball ? &corr : NULL);
+        if (st != OR_OK) {
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+          {
+            if (status == OR_OK) { status = st; ba = a; bb = b; }
+          }
+        }
+        Mall[(int64_t)a * r + b] = I;
+        Mall[(int64_t)b * r + a] = -I;
+        if (Ball) Ball[(int64_t)a * r + b] = Ball[(int64_t)b * r + a] = corr;
+      }
+    }
+    free(scratch);
+  }
+  if (status == OR_OK) {
+    for (int32_t a = 0; a < r; ++a) {
+      csum s = {0, 0};
+      for (int32_t b = 0; b < r; ++b) {
+        if (b == a) continue;
+        double m = Mall[(int64_t)a * r + b] < 0.0 ? Mall[(int64_t)a * r + b] : 0.0;
+        cs_add(&s, m * m);
+      }
+      S[a] = cs_val(&s);
+    }
+    if (Mrow) memcpy(Mrow, Mall, sizeof(double) * (size_t)r * (size_t)r);
+    if (Brow) memcpy(Brow, Ball, sizeof(double) * (size_t)r * (size_t)r);
+  }
+  free(Mall); free(Ball);
   if (bad_a) *bad_a = ba;
   if (bad_b) *bad_b = bb;
   return status;
@@ -308,12 +390,14 @@ static void regress_root(double* X, const double* Z, int64_t n, const int32_t* U
  *   Bout      : optional [M_iters*p*p] out, correlation of the normalised pair
  *               (i, j) at iteration t (the regression coefficient), NaN where undefined
  *   bad_i/j   : variables of a degenerate or non-finite input
+ *   pair_once : evaluate each unordered pair once and take the reverse test as
+ *               its negation (bitwise the same outputs, half the work)
  * Returns OR_OK or an error status.
  */
 int oracle_fit_order(const double* X, int64_t n, int64_t p, int32_t max_roots,
                      const int32_t* forced, int32_t forced_len, int32_t nthreads,
                      int32_t* order, double* T, double* Hout, double* M, double* Bout,
-                     int32_t M_iters, int32_t* bad_i, int32_t* bad_j) {
+                     int32_t M_iters, int32_t* bad_i, int32_t* bad_j, int32_t pair_once) {
   if (!X || !order || n < 2 || p < 1) return OR_E_INVALID;
   if (forced_len < 0 || (forced_len > 0 && !forced)) return OR_E_INVALID;
   if (bad_i) *bad_i = -1;
@@ -363,7 +447,7 @@ int oracle_fit_order(const double* X, int64_t n, int64_t p, int32_t max_roots,
       int32_t ba = -1, bb = -1;
       const int rec = t < M_iters;
       status = find_root_scores(Z, n, U, r, H, S, rec ? Mr : NULL, rec ? Br : NULL, NULL,
-                                nthreads, &ba, &bb);
+                                nthreads, &ba, &bb, pair_once);
       if (status != OR_OK) {
         if (bad_i) *bad_i = ba >= 0 ? U[ba] : -1;
         if (bad_j) *bad_j = bb >= 0 ? U[bb] : -1;
@@ -458,7 +542,7 @@ int oracle_sampled_at(const double* X, int64_t n, int64_t p, const int32_t* pref
         status = OR_E_INVALID;
   }
   if (status == OR_OK && nvars > 0) {
-    status = find_root_scores(Z, n, U, r, H, S, NULL, NULL, only, nthreads, NULL, NULL);
+    status = find_root_scores(Z, n, U, r, H, S, NULL, NULL, only, nthreads, NULL, NULL, 0);
     if (status == OR_OK)
       for (int32_t k = 0; k < nvars; ++k) T_out[k] = -S[pos[vars[k]]];
   }

@@ -20,12 +20,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblingam.so")
 
 OK, E_INVALID, E_NONFINITE, E_DEGENERATE, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(7)
-PREC = {"fp64": 0, "mixed": 1, "fp32": 1}
+PREC = {"fp64": 0, "mixed": 1, "fp32": 1, "fp32_storage": 2}
 LAYOUT = {"var_major": 0, "sample_major": 1}
 
 # Exported symbols of the C ABI (kept in sync with include/lingam.h).
 SYMBOLS = ("lingam_opts_default", "lingam_fit_order", "lingam_fit_order_batch",
-           "lingam_workspace_size", "lingam_status_string", "lingam_last_error")
+           "lingam_workspace_size", "lingam_workspace_size_batch", "lingam_estimate_B",
+           "lingam_status_string", "lingam_last_error")
 
 
 class LingamOpts(ctypes.Structure):
@@ -48,6 +49,13 @@ class LingamOpts(ctypes.Structure):
         ("chunk_samples", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
         ("profile", ctypes.c_int32),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_uint64),
+        ("estimate_B", ctypes.c_int32),
+        ("batch_queue", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
+        ("band_target", ctypes.c_double),
+        ("first_band_blocks", ctypes.c_int32),
     ]
 
 
@@ -59,6 +67,7 @@ class LingamResult(ctypes.Structure):
         ("H", ctypes.POINTER(ctypes.c_double)),
         ("M", ctypes.POINTER(ctypes.c_double)),
         ("T_err_bound", ctypes.POINTER(ctypes.c_double)),
+        ("B", ctypes.POINTER(ctypes.c_double)),
         ("pairs_evaluated", ctypes.c_uint64),
         ("pair_samples", ctypes.c_uint64),
         ("pairs_computed", ctypes.c_uint64),
@@ -114,6 +123,13 @@ def load_library(path: str = LIB_PATH):
                                            ctypes.POINTER(LingamOpts), ctypes.POINTER(LingamResult)]
     lib.lingam_workspace_size.restype = ctypes.c_uint64
     lib.lingam_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(LingamOpts)]
+    lib.lingam_workspace_size_batch.restype = ctypes.c_uint64
+    lib.lingam_workspace_size_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(LingamDataset),
+                                                ctypes.POINTER(LingamOpts)]
+    lib.lingam_estimate_B.restype = ctypes.c_int
+    lib.lingam_estimate_B.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(LingamOpts),
+                                      ctypes.POINTER(ctypes.c_double)]
     lib.lingam_status_string.restype = ctypes.c_char_p
     lib.lingam_status_string.argtypes = [ctypes.c_int]
     lib.lingam_last_error.restype = ctypes.c_char_p
@@ -130,6 +146,7 @@ class FitResult:
     H: Optional[np.ndarray] = None    # [p, p] entropy of v at iteration t
     M: Optional[np.ndarray] = None    # [k, p, p] test matrices of the first k iterations
     T_err: Optional[np.ndarray] = None  # [p, p] rounding bound of T (mixed; 0 in FP64 mode)
+    B: Optional[np.ndarray] = None    # [p, p] causal strengths (estimate_B), B[i, j] = effect of x_j on x_i
     pairs_evaluated: int = 0
     pair_samples: int = 0
     pairs_computed: int = 0
@@ -174,22 +191,54 @@ def _make_opts(precision="fp64", use_threshold=True, gamma0=0.0, gamma_mult=0.0,
     return o, keep
 
 
+def _apply_tuned(o, kind, precision, p, n, queue=None, graph=None):
+    """Fill the launch parameters the caller left at their defaults from the
+    autotuner's entry for this device and problem bucket, if any."""
+    from . import autotune
+    t = autotune.lookup(kind, precision, p, n)
+    if not t:
+        return
+    if o.chunk_samples == 0 and "chunk_samples" in t:
+        o.chunk_samples = int(t["chunk_samples"])
+    if o.band_blocks == 0 and o.first_band_blocks == 0 and "first_band_blocks" in t:
+        o.first_band_blocks = int(t["first_band_blocks"])
+    if o.band_target == 0.0 and "band_target" in t:
+        o.band_target = float(t["band_target"])
+    if queue is None and "batch_queue" in t:
+        o.batch_queue = int(t["batch_queue"])
+    if graph is None and "graph" in t and o.workspace:
+        o.graph = int(t["graph"])
+
+
 def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: float = 0.0,
               gamma_mult: float = 0.0, cov_refresh_every=None, max_roots: int = 0,
               forced_order=None, record_M_iters: int = 0, want_T: bool = True,
               want_H: bool = True, band_blocks: int = 0, chunk_samples: int = 0,
-              layout: str = "var_major", stream=None, profile: bool = False) -> FitResult:
+              layout: str = "var_major", stream=None, profile: bool = False,
+              workspace=None, estimate_B: bool = False,
+              band_target: float = 0.0, first_band_blocks: int = 0, tune: bool = True) -> FitResult:
     """Causal order of the variables of X (lingam_fit_order).
 
     X is a p x n array (row i = samples of variable i; layout="sample_major"
     for n x p) of float64 or float32: a numpy array (copied to the device by the
     library) or a torch tensor (a CUDA/HIP tensor is used in place on its
     device and on `stream`, default the current torch stream).
+    workspace: optional device tensor (e.g. torch.empty(nbytes, dtype=torch.uint8,
+    device="cuda")) that the call carves its device buffers from
+    (workspace_size() bytes at least).
+    estimate_B: also estimate the causal strengths B from the order (result.B).
+    band_target / chunk_samples / band_blocks: launch tuning (never changes a
+    result); left at 0 they take the autotuner's entry for this device and
+    problem bucket when there is one (tune=True), else the library defaults.
     """
     lib = load_library()
     o, keep = _make_opts(precision, use_threshold, gamma0, gamma_mult, cov_refresh_every,
                          max_roots, forced_order, record_M_iters, band_blocks, chunk_samples, layout,
                          profile=profile)
+    if workspace is not None:
+        o.workspace = ctypes.c_void_p(workspace.data_ptr())
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    o.estimate_B = 1 if estimate_B else 0
     is_torch = type(X).__module__.startswith("torch")
     if is_torch:
         import torch
@@ -219,12 +268,17 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
     if len(shape) != 2:
         raise ValueError("X must be 2-D")
     p, n = (shape[0], shape[1]) if layout == "var_major" else (shape[1], shape[0])
+    o.band_target = float(band_target)
+    o.first_band_blocks = int(first_band_blocks)
+    if tune:
+        _apply_tuned(o, "single", precision, p, n)
     order = np.full(p, -1, dtype=np.int32)
     T = np.full((p, p), np.nan) if want_T else None
     Ts = np.zeros((p, p), dtype=np.uint8) if want_T else None
     H = np.full((p, p), np.nan) if want_H else None
     Terr = np.full((p, p), np.nan) if want_T else None
     M = np.full((record_M_iters, p, p), np.nan) if record_M_iters > 0 else None
+    Bm = np.full((p, p), np.nan) if estimate_B else None
     res = LingamResult()
     res.order = order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     if T is not None:
@@ -236,11 +290,13 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
         res.T_err_bound = Terr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     if M is not None:
         res.M = M.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if Bm is not None:
+        res.B = Bm.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     st = lib.lingam_fit_order(ctypes.c_void_p(ptr), n, p, ctypes.byref(o), ctypes.byref(res))
     del host_ref, keep
     if st != OK:
         raise LingamError(st, lib.lingam_last_error().decode(), res.bad_i, res.bad_j)
-    return FitResult(order=order, T=T, T_state=Ts, H=H, M=M, T_err=Terr,
+    return FitResult(order=order, T=T, T_state=Ts, H=H, M=M, T_err=Terr, B=Bm,
                      pairs_evaluated=res.pairs_evaluated, pair_samples=res.pair_samples,
                      pairs_computed=res.pairs_computed, threshold_rounds=res.threshold_rounds,
                      bands=res.bands, seconds_total=res.seconds_total,
@@ -251,7 +307,9 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
 def fit_order_batch(datasets, precision: str = "fp64", use_threshold: bool = True, gamma0: float = 0.0,
                     gamma_mult: float = 0.0, cov_refresh_every=None, max_roots: int = 0,
                     band_blocks: int = 0, chunk_samples: int = 0, want_T: bool = True,
-                    want_H: bool = False, profile: bool = False, stream=None):
+                    want_H: bool = False, profile: bool = False, stream=None, queue=None,
+                    workspace=None, graph=None, band_target: float = 0.0, first_band_blocks: int = 0,
+                    tune: bool = True):
     """Causal orders of many data sets in one batched search (lingam_fit_order_batch).
 
     `datasets` is a list whose items are either a p x n array (numpy, float64
@@ -263,6 +321,18 @@ def fit_order_batch(datasets, precision: str = "fp64", use_threshold: bool = Tru
     lib = load_library()
     o, _ = _make_opts(precision, use_threshold, gamma0, gamma_mult, cov_refresh_every, max_roots,
                       None, 0, band_blocks, chunk_samples, profile=profile)
+    o.band_target = float(band_target)
+    o.first_band_blocks = int(first_band_blocks)
+    if workspace is not None:
+        o.workspace = ctypes.c_void_p(workspace.data_ptr())
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    if tune:
+        from . import autotune
+        _apply_tuned(o, "batch", precision, *autotune.batch_shape(datasets), queue=queue, graph=graph)
+    if queue is not None:
+        o.batch_queue = 1 if queue else 0
+    if graph is not None:
+        o.graph = 1 if graph else 0
     if stream is not None:
         o.stream = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
     count = len(datasets)
@@ -326,10 +396,73 @@ def fit_order_batch(datasets, precision: str = "fp64", use_threshold: bool = Tru
     return res
 
 
+def estimate_B(X, order, precision: str = "fp64", layout: str = "var_major", stream=None) -> np.ndarray:
+    """Causal strengths B of X along a causal order (lingam_estimate_B): each
+    variable regressed by least squares on every variable before it in
+    `order`.  Returns B (p x p float64), B[i, j] = coefficient of x_j for x_i."""
+    lib = load_library()
+    o, _ = _make_opts(precision, layout=layout)
+    is_torch = type(X).__module__.startswith("torch")
+    if is_torch:
+        import torch
+        X = X.contiguous()
+        o.x_dtype = 0 if X.dtype == torch.float64 else 1
+        ptr, shape, keep = X.data_ptr(), tuple(X.shape), X
+        if X.is_cuda:
+            o.x_on_device = 1
+            o.device = X.device.index if X.device.index is not None else torch.cuda.current_device()
+            s = stream if stream is not None else torch.cuda.current_stream(X.device)
+            o.stream = ctypes.c_void_p(s.cuda_stream if hasattr(s, "cuda_stream") else int(s))
+    else:
+        keep = np.ascontiguousarray(X if np.asarray(X).dtype in (np.float64, np.float32)
+                                    else np.asarray(X, dtype=np.float64))
+        o.x_dtype = 0 if keep.dtype == np.float64 else 1
+        ptr, shape = keep.ctypes.data, keep.shape
+    p, n = (shape[0], shape[1]) if layout == "var_major" else (shape[1], shape[0])
+    K = np.ascontiguousarray(order, dtype=np.int32)
+    B = np.full((p, p), np.nan)
+    st = lib.lingam_estimate_B(ctypes.c_void_p(ptr), n, p, K.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               ctypes.byref(o), B.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    del keep
+    if st != OK:
+        raise LingamError(st, lib.lingam_last_error().decode())
+    return B
+
+
 def status_string(status: int) -> str:
     return load_library().lingam_status_string(int(status)).decode()
 
 
-def workspace_size(n: int, p: int, precision: str = "fp64") -> int:
+def batch_workspace_size(datasets, precision: str = "fp64") -> int:
+    """Device bytes of one fit_order_batch call over `datasets` (host inputs,
+    as fit_order_batch takes them): lingam_workspace_size_batch."""
     o, _ = _make_opts(precision)
+    count = len(datasets)
+    sets = (LingamDataset * count)()
+    keep = []
+    for k, item in enumerate(datasets):
+        if isinstance(item, tuple):
+            base, idx = item
+            base = np.ascontiguousarray(base, dtype=np.float64)
+            idx = np.ascontiguousarray(idx, dtype=np.int64)
+            keep += [base, idx]
+            sets[k].X = ctypes.c_void_p(base.ctypes.data)
+            sets[k].p, sets[k].n = base.shape
+            sets[k].sample_idx = idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            sets[k].n_idx = idx.size
+        else:
+            arr = np.ascontiguousarray(item)
+            keep.append(arr)
+            o.x_dtype = 1 if arr.dtype == np.float32 else 0
+            sets[k].X = ctypes.c_void_p(arr.ctypes.data)
+            sets[k].p, sets[k].n = arr.shape
+    return int(load_library().lingam_workspace_size_batch(count, sets, ctypes.byref(o)))
+
+
+def workspace_size(n: int, p: int, precision: str = "fp64", x_on_device: bool = False,
+                   x_dtype: str = "float64", record_M_iters: int = 0) -> int:
+    """Device bytes of one fit_order call (lingam_workspace_size)."""
+    o, _ = _make_opts(precision, record_M_iters=record_M_iters)
+    o.x_on_device = 1 if x_on_device else 0
+    o.x_dtype = 1 if x_dtype == "float32" else 0
     return int(load_library().lingam_workspace_size(n, p, ctypes.byref(o)))

@@ -8,7 +8,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblingam.so")
-SOURCES = ["kernels.hip", "driver.cpp"]
+# every HIP and host source of csrc/ (the host sources are compiled as HIP too)
+SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 ARCH = os.environ.get("LINGAM_OFFLOAD_ARCH", "gfx950")
 
 # Packed binary32 VALU forms are disabled for all device code.

@@ -23,6 +23,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -44,20 +46,52 @@ struct HipFail {
     if (e_ != hipSuccess) throw HipFail{e_, #x, __LINE__}; \
   } while (0)
 
-// Device allocations of one call, released on every exit path.
-struct Allocs {
-  std::vector<void*> ptrs;
-  ~Allocs() {
-    for (void* q : ptrs) (void)hipFree(q);
-  }
+struct NoMem {
+  uint64_t need, have;
+};
+
+// Device memory of one call, carved out of one block: the caller's
+// workspace, the no-allocation entry point's static device array, or one
+// hipMalloc of the whole size.  A sizing pass (base == nullptr) runs the same
+// sequence of get() calls and only counts bytes, so the size a call needs
+// and the layout it uses come from one piece of code.  Every buffer starts
+// on a 256-byte boundary.
+struct Arena {
+  char* base = nullptr;
+  uint64_t off = 0, cap = 0;
   template <class T>
   T* get(size_t count) {
-    void* q = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&q, count * sizeof(T));
-    if (e != hipSuccess) throw HipFail{e, "hipMalloc", __LINE__};
-    ptrs.push_back(q);
-    return static_cast<T*>(q);
+    off = (off + 255) & ~(uint64_t)255;
+    const uint64_t at = off;
+    off += (uint64_t)count * sizeof(T);
+    if (!base) return nullptr;
+    if (off > cap) throw NoMem{off, cap};
+    return reinterpret_cast<T*>(base + at);
+  }
+};
+
+// One hipMalloc of a call's whole workspace, released on every exit path.
+struct OwnedMem {
+  void* p = nullptr;
+  ~OwnedMem() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+// Restores the calling thread's current device on every exit path.
+struct DeviceGuard {
+  int prev = -1;
+  void set(int dev) {
+    if (dev < 0) return;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+    if (cur == dev) return;
+    prev = cur;
+    if (hipSetDevice(dev) != hipSuccess) throw HipFail{hipErrorInvalidDevice, "hipSetDevice", __LINE__};
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
   }
 };
 
@@ -96,11 +130,12 @@ struct Plan {
 Plan make_plan(int64_t n, const lingam_opts& o, bool single) {
   Plan pl;
   int chunk = o.chunk_samples > 0 ? o.chunk_samples : CHUNK_DEFAULT;
-  if (o.precision == LINGAM_PREC_MIXED) chunk = std::min(chunk, CHUNK_MAX_MIXED);
+  if (o.precision != LINGAM_PREC_FP64) chunk = std::min(chunk, CHUNK_MAX_MIXED);
   pl.chunk = chunk;
   pl.nchunk = (int)((n + chunk - 1) / chunk);
   pl.band_blocks = o.band_blocks > 0 ? o.band_blocks
-                 : (single && o.precision == LINGAM_PREC_MIXED ? BAND_BLOCKS_SINGLE_MIXED : BAND_BLOCKS_DEFAULT);
+                 : o.first_band_blocks > 0 ? o.first_band_blocks
+                 : (single && o.precision != LINGAM_PREC_FP64 ? BAND_BLOCKS_SINGLE_MIXED : BAND_BLOCKS_DEFAULT);
   return pl;
 }
 
@@ -120,7 +155,8 @@ lingam_status fail(lingam_status st, const std::string& msg) {
 
 lingam_status validate_opts(const lingam_opts& o) {
   if (o.struct_size != sizeof(lingam_opts)) return fail(LINGAM_E_INVALID, "opts.struct_size mismatch");
-  if (o.precision != LINGAM_PREC_FP64 && o.precision != LINGAM_PREC_MIXED)
+  if (o.precision != LINGAM_PREC_FP64 && o.precision != LINGAM_PREC_MIXED &&
+      o.precision != LINGAM_PREC_FP32_STORAGE)
     return fail(LINGAM_E_INVALID, "unknown precision");
   if (o.layout != LINGAM_LAYOUT_VAR_MAJOR && o.layout != LINGAM_LAYOUT_SAMPLE_MAJOR)
     return fail(LINGAM_E_INVALID, "unknown layout");
@@ -129,7 +165,12 @@ lingam_status validate_opts(const lingam_opts& o) {
   if (o.chunk_samples < 0 || o.chunk_samples % SUB != 0)
     return fail(LINGAM_E_INVALID, "chunk_samples must be a multiple of 256");
   if (o.band_blocks < 0) return fail(LINGAM_E_INVALID, "band_blocks < 0");
+  if (o.first_band_blocks < 0) return fail(LINGAM_E_INVALID, "first_band_blocks < 0");
   if (o.record_M_iters < 0) return fail(LINGAM_E_INVALID, "record_M_iters < 0");
+  if (o.estimate_B != 0 && o.estimate_B != 1) return fail(LINGAM_E_INVALID, "estimate_B must be 0 or 1");
+  if (o.batch_queue != 0 && o.batch_queue != 1) return fail(LINGAM_E_INVALID, "batch_queue must be 0 or 1");
+  if (o.graph != 0 && o.graph != 1) return fail(LINGAM_E_INVALID, "graph must be 0 or 1");
+  if (!(o.band_target >= 0.0) || o.band_target > 1e15) return fail(LINGAM_E_INVALID, "band_target out of range");
   if (o.forced_len < 0 || (o.forced_len > 0 && !o.forced_order))
     return fail(LINGAM_E_INVALID, "bad forced_order / forced_len");
   return LINGAM_OK;
@@ -152,6 +193,11 @@ lingam_status validate(const void* X, int64_t n, int64_t p, const lingam_opts& o
   if (st != LINGAM_OK) return st;
   if (o.record_M_iters > p) return fail(LINGAM_E_INVALID, "record_M_iters out of range");
   if (o.record_M_iters > 0 && !out->M) return fail(LINGAM_E_INVALID, "record_M_iters > 0 but result->M is NULL");
+  if (o.estimate_B) {
+    if (!out->B) return fail(LINGAM_E_INVALID, "estimate_B set but result->B is NULL");
+    if (o.max_roots > 0 && o.max_roots < p) return fail(LINGAM_E_INVALID, "estimate_B needs the full order");
+    if (p > B_MAX_P) return fail(LINGAM_E_INVALID, "estimate_B supports p <= 8000");
+  }
   if (o.forced_len > p) return fail(LINGAM_E_INVALID, "bad forced_order / forced_len");
   if (o.forced_len > 0) {
     std::vector<char> seen((size_t)p, 0);
@@ -171,6 +217,7 @@ void reset_result(lingam_result* out, int64_t p, int rec) {
   if (out->H) for (int64_t k = 0; k < p * p; ++k) out->H[k] = NAN;
   if (out->M) for (int64_t k = 0; k < (int64_t)rec * p * p; ++k) out->M[k] = NAN;
   if (out->T_err_bound) for (int64_t k = 0; k < p * p; ++k) out->T_err_bound[k] = NAN;
+  if (out->B) for (int64_t k = 0; k < p * p; ++k) out->B[k] = NAN;
   out->pairs_evaluated = out->pair_samples = out->pairs_computed = 0;
   out->threshold_rounds = out->bands = 0;
   out->seconds_total = out->seconds_device = out->seconds_pair_kernel = 0.0;
@@ -217,18 +264,20 @@ struct SetInfo {
   Ctl* ctl = nullptr;   // its control block inside the call's Ctl array
 };
 
-Dev alloc_set(Allocs& al, int64_t n, int64_t p, const Plan& pl, const lingam_opts& o, bool mixed, Ctl* ctl) {
+Dev carve_set(Arena& al, int64_t n, int64_t p, const Plan& pl, const lingam_opts& o, bool mixed, Ctl* ctl) {
   Dev d;
   d.p = (int)p;
   d.n = n;
   d.ldz = round_up(n, SUB);
   d.nchunk = (int)((n + pl.chunk - 1) / pl.chunk);
   d.mixed = mixed ? 1 : 0;
+  d.store32 = o.precision == LINGAM_PREC_FP32_STORAGE ? 1 : 0;
   d.x_dtype = o.x_dtype;
   d.layout = o.layout;
   const size_t P = (size_t)p, pp = P * P;
-  d.Z[0] = al.get<double>(P * d.ldz);
-  d.Z[1] = al.get<double>(P * d.ldz);
+  const size_t zbytes = P * (size_t)d.ldz * (d.store32 ? sizeof(float) : sizeof(double));
+  d.Z[0] = al.get<uint8_t>(zbytes);
+  d.Z[1] = al.get<uint8_t>(zbytes);
   d.Sig[0] = al.get<double>(pp);
   d.Sig[1] = al.get<double>(pp);
   d.dsc[0] = al.get<double>(P);
@@ -265,6 +314,11 @@ Dev alloc_set(Allocs& al, int64_t n, int64_t p, const Plan& pl, const lingam_opt
   int32_t* forced_dev = al.get<int32_t>(std::max<size_t>(1, (size_t)o.forced_len));
   d.forced = forced_dev;
   d.pair_slots = al.get<unsigned long long>(2 * PAIR_SLOTS);
+  if (o.estimate_B) {
+    d.C0 = al.get<double>(pp);
+    d.Lch = al.get<double>(pp);
+    d.Bout = al.get<double>(pp);
+  }
   d.band_k0 = pl.band_blocks;
   d.band_adapt = o.band_blocks > 0 ? 0 : 1;
   return d;
@@ -279,7 +333,9 @@ void init_set(const Dev& d, const lingam_opts& o, int limit, hipStream_t s, std:
                           hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(d.idx[0], iota.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(d.ord[0], iota.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
-  HIPCHK(launch_fill(d.Z[1], (int64_t)(P * d.ldz), 0.0, s));
+  // zero padding past n in the second row buffer (the first is written whole by the normalisation)
+  HIPCHK(launch_fill_u8(static_cast<uint8_t*>(d.Z[1]),
+                        (int64_t)(P * d.ldz * (d.store32 ? sizeof(float) : sizeof(double))), 0, s));
   HIPCHK(launch_fill(d.M, (int64_t)pp, NAN, s));
   HIPCHK(launch_fill_u8(d.pend, (int64_t)pp, 0, s));
   HIPCHK(launch_fill(d.Tall, (int64_t)pp, NAN, s));
@@ -326,6 +382,7 @@ struct Fit {
     BandArgs a{pl.chunk, 1, 1, BAND_TARGET_DEFAULT};
     pair_band_shape(b, a.rows_per_group, a.groups);
     if (b.count == 1 && b.mixed) a.band_target = BAND_TARGET_SINGLE_MIXED;
+    if (o.band_target > 0.0) a.band_target = o.band_target;
     pair(t, a, first, hint);
     HIPCHK(launch_score(b, t, a, gmult, first ? 1 : 0, hint, s));
   }
@@ -460,7 +517,400 @@ void set_error_text(lingam_status st, const lingam_result* out) {
   g_last_error = buf;
 }
 
+
+// ---- device memory of a call ---------------------------------------------
+
+size_t x_bytes(int64_t n, int64_t p, const lingam_opts& o) {
+  return (size_t)p * (size_t)n * (o.x_dtype == 1 ? 4 : 8);
+}
+
+// Buffers of a single search (one data set), in carve order.
+struct SingleLayout {
+  Ctl* ctl = nullptr;
+  Dev d;
+  void* xb = nullptr;   // staging of a host X
+  Dev* dd = nullptr;    // device copy of the descriptor
+};
+
+SingleLayout layout_single(Arena& ar, int64_t n, int64_t p, const Plan& pl, const lingam_opts& o) {
+  SingleLayout L;
+  L.ctl = ar.get<Ctl>(1);
+  L.d = carve_set(ar, n, p, pl, o, o.precision != LINGAM_PREC_FP64, L.ctl);
+  if (!o.x_on_device) L.xb = ar.get<uint8_t>(x_bytes(n, p, o));
+  L.dd = ar.get<Dev>(1);
+  return L;
+}
+
+// Buffers of a batch, in carve order.  A bootstrap base (identified by its
+// X pointer) is staged once; every bootstrap set gets its index vector and
+// its gathered rows.
+struct BatchLayout {
+  Ctl* ctls = nullptr;
+  std::vector<Dev> devs;
+  std::vector<void*> xb;            // per set: staging of a host X (or nullptr)
+  std::vector<const double*> base;  // per bootstrap set: its base rows on the device
+  std::vector<char> base_upload;    // per set: 1 if this set's base is uploaded here
+  std::vector<int64_t*> idx;        // per bootstrap set: device sample indices
+  Dev* dd = nullptr;
+};
+
+BatchLayout layout_batch(Arena& ar, int32_t count, const lingam_dataset* sets, const Plan& pl,
+                         const lingam_opts& o) {
+  BatchLayout L;
+  const bool mixed = o.precision != LINGAM_PREC_FP64;
+  L.ctls = ar.get<Ctl>((size_t)count);
+  L.devs.resize((size_t)count);
+  L.xb.assign((size_t)count, nullptr);
+  L.base.assign((size_t)count, nullptr);
+  L.base_upload.assign((size_t)count, 0);
+  L.idx.assign((size_t)count, nullptr);
+  std::vector<std::pair<const void*, const double*>> bases;
+  for (int k = 0; k < count; ++k) {
+    const lingam_dataset& ds = sets[k];
+    const int64_t nk = ds.sample_idx ? ds.n_idx : ds.n, pk = ds.p;
+    Dev d = carve_set(ar, nk, pk, pl, o, mixed, L.ctls ? L.ctls + k : nullptr);
+    if (ds.sample_idx) {
+      const double* base = nullptr;
+      bool found = false;
+      for (auto& bp : bases)
+        if (bp.first == ds.X) { base = bp.second; found = true; }
+      if (!found) {
+        if (o.x_on_device) {
+          base = (const double*)ds.X;
+        } else {
+          base = ar.get<double>((size_t)pk * (size_t)ds.n);
+          L.base_upload[(size_t)k] = 1;
+        }
+        bases.push_back({ds.X, base});
+      }
+      L.base[(size_t)k] = base;
+      L.idx[(size_t)k] = ar.get<int64_t>((size_t)ds.n_idx);
+      d.X = ar.get<double>((size_t)pk * (size_t)nk);   // the gathered resample
+      d.x_dtype = 0;
+      d.layout = 0;
+    } else if (!o.x_on_device) {
+      L.xb[(size_t)k] = ar.get<uint8_t>(x_bytes(nk, pk, o));
+      d.X = L.xb[(size_t)k];
+    } else {
+      d.X = ds.X;
+    }
+    L.devs[(size_t)k] = d;
+  }
+  L.dd = ar.get<Dev>((size_t)count);
+  return L;
+}
+
+// Where a call's device memory comes from: the caller's workspace
+// (opts.workspace), else one hipMalloc of the size the sizing pass found.
+// Checks the caller's workspace on the host, before any device work.
+lingam_status acquire(uint64_t need, const lingam_opts& o, OwnedMem& own, Arena& ar) {
+  if (o.workspace) {
+    if ((reinterpret_cast<uintptr_t>(o.workspace) & 255u) != 0)
+      return fail(LINGAM_E_INVALID, "opts.workspace must be 256-byte aligned");
+    if (o.workspace_bytes < need) {
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "opts.workspace holds %llu bytes, the call needs %llu",
+                    (unsigned long long)o.workspace_bytes, (unsigned long long)need);
+      return fail(LINGAM_E_NOMEM, buf);
+    }
+    ar.base = static_cast<char*>(o.workspace);
+    ar.cap = o.workspace_bytes;
+    return LINGAM_OK;
+  }
+  hipError_t e = hipMalloc(&own.p, need);
+  if (e != hipSuccess) {
+    own.p = nullptr;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "hipMalloc of %llu bytes failed: %s", (unsigned long long)need,
+                  hipGetErrorString(e));
+    return fail(e == hipErrorOutOfMemory ? LINGAM_E_NOMEM : LINGAM_E_DEVICE, buf);
+  }
+  ar.base = static_cast<char*>(own.p);
+  ar.cap = need;
+  return LINGAM_OK;
+}
+
+// One causal-order search.  fixed == nullptr: the device memory is the
+// caller's workspace or one hipMalloc; otherwise it is the block
+// [fixed->base, fixed->base + fixed->cap) on the current device, and the call
+// allocates nothing (no device memory, streams or events are created; the
+// search runs on opts.stream, NULL = the null stream).
+// given_order (optional, host): skip the search and estimate B along this
+// order (lingam_estimate_B).
+lingam_status fit_single(const void* X, int64_t n, int64_t p, const lingam_opts& o, lingam_result* out,
+                         const FixedBlock* fixed, const int32_t* given_order = nullptr) {
+  const auto wall0 = std::chrono::steady_clock::now();
+  g_last_error.clear();
+  lingam_status st = validate(X, n, p, o, out);
+  if (st != LINGAM_OK) return st;
+  if (fixed) {
+    if (o.workspace) return fail(LINGAM_E_INVALID, "this entry point takes no opts.workspace");
+    if (o.profile) return fail(LINGAM_E_UNSUPPORTED, "opts.profile needs timing events, which allocate");
+  }
+  reset_result(out, p, o.record_M_iters);
+
+  const Plan pl = make_plan(n, o, true);
+  Arena sizing;
+  (void)layout_single(sizing, n, p, pl, o);
+  const uint64_t need = sizing.off;
+  if (fixed && need > fixed->cap) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf, "p=%lld n=%lld needs %llu bytes of device memory; %s holds at most %llu",
+                  (long long)p, (long long)n, (unsigned long long)need, fixed->who,
+                  (unsigned long long)fixed->cap);
+    return fail(LINGAM_E_NOMEM, buf);
+  }
+
+  OwnedMem own;
+  OwnedStream os;
+  PairTimer timer;
+  DeviceGuard dg;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  const bool events = fixed == nullptr;
+  try {
+    dg.set(o.device);
+    Arena ar;
+    if (fixed) {
+      ar.base = fixed->base;
+      ar.cap = fixed->cap;
+    } else {
+      st = acquire(need, o, own, ar);
+      if (st != LINGAM_OK) return st;
+    }
+    SingleLayout L = layout_single(ar, n, p, pl, o);
+    if (o.stream || fixed) {
+      os.s = (hipStream_t)o.stream;
+    } else {
+      HIPCHK(hipStreamCreate(&os.s));
+      os.owned = true;
+    }
+    Fit f;
+    f.timer = &timer;
+    timer.on = o.profile != 0;
+    f.o = o;
+    f.s = os.s;
+    f.refresh_every = o.cov_refresh_every >= 0 ? o.cov_refresh_every
+                      : (o.precision != LINGAM_PREC_FP64 ? REFRESH_MIXED : 1);
+    const bool mixed = o.precision != LINGAM_PREC_FP64;
+    f.threshold = o.use_threshold != 0;
+    f.gamma0 = o.gamma0 > 0 ? o.gamma0 : 0.0;  // 0 = adaptive
+    f.gmult = o.gamma_mult > 1.0 ? o.gamma_mult : 4.0;
+    f.pl = pl;
+    f.rec = o.record_M_iters;
+    const int limit = (o.max_roots > 0 && o.max_roots < p) ? o.max_roots : (int)p;
+    f.ps = {p};
+    f.limits = {limit};
+
+    Dev& d = L.d;
+    d.limit = limit;
+    if (!o.x_on_device) {
+      HIPCHK(hipMemcpyAsync(L.xb, X, x_bytes(n, p, o), hipMemcpyHostToDevice, f.s));
+      d.X = L.xb;
+    } else {
+      d.X = X;
+    }
+    HIPCHK(hipMemcpyAsync(L.dd, &d, sizeof(Dev), hipMemcpyHostToDevice, f.s));
+    std::vector<int32_t> iota((size_t)p);
+    for (int64_t k = 0; k < p; ++k) iota[(size_t)k] = (int32_t)k;
+    init_set(d, o, limit, f.s, iota);
+    Ctl c0;
+    std::memset(&c0, 0, sizeof(c0));
+    c0.halt_iter = -1;
+    c0.root = -1;
+    c0.bad_i = c0.bad_j = -1;
+    HIPCHK(hipMemcpyAsync(L.ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, f.s));
+    HIPCHK(hipStreamSynchronize(f.s));  // host temporaries (d, iota, c0) are no longer needed
+
+    f.b.dd = L.dd;
+    f.b.count = 1;
+    f.b.one = d;
+    f.b.p_max = (int)p;
+    f.b.n_max = n;
+    f.b.nchunk_max = d.nchunk;
+    f.b.gram_slices_max = GRAM_SLICES_MAX;
+    f.b.mixed = mixed ? 1 : 0;
+    f.b.store32 = o.precision == LINGAM_PREC_FP32_STORAGE ? 1 : 0;
+    f.b.queue = o.batch_queue ? 1 : 0;
+
+    if (events) {
+      HIPCHK(hipEventCreate(&ev0));
+      HIPCHK(hipEventCreate(&ev1));
+      HIPCHK(hipEventRecord(ev0, f.s));
+    }
+    // a1 + a2: normalise once, covariance once (Alg. 3)
+    HIPCHK(launch_standardize(f.b, f.s));
+    HIPCHK(launch_gram(f.b, 0, 0, f.s));
+    if (o.estimate_B) HIPCHK(launch_corr_snapshot(d, f.s));
+    Ctl c;
+    if (given_order) {
+      HIPCHK(hipMemcpyAsync(d.order, given_order, sizeof(int32_t) * p, hipMemcpyHostToDevice, f.s));
+      c = f.read_ctl(L.ctl);
+    } else {
+      c = f.drive_one(L.ctl, 0, limit, (int)p);
+    }
+    // Alg. 1, last step: the causal strengths along the order
+    if (o.estimate_B && c.status == ST_OK) {
+      HIPCHK(launch_estimate_B(d, f.s));
+      c = f.read_ctl(L.ctl);
+      if (c.status == ST_OK)
+        HIPCHK(hipMemcpyAsync(out->B, d.Bout, sizeof(double) * p * p, hipMemcpyDeviceToHost, f.s));
+    }
+    if (events) HIPCHK(hipEventRecord(ev1, f.s));
+    copy_results(d, c, n, out, f.s);
+    float ms = 0.f;
+    if (events && hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) out->seconds_device = ms * 1e-3;
+    if (timer.on) {
+      out->seconds_pair_kernel = timer.total_seconds();
+      out->pair_kernel_launches = timer.launches;
+    }
+    st = (lingam_status)out->status;
+    if (st != LINGAM_OK) set_error_text(st, out);
+  } catch (const HipFail& e) {
+    st = status_from(e);
+    out->status = st;
+  } catch (const NoMem& e) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "workspace layout needs %llu bytes, %llu available",
+                  (unsigned long long)e.need, (unsigned long long)e.have);
+    st = fail(LINGAM_E_NOMEM, buf);
+    out->status = st;
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  out->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+  return st;
+}
+
+// ---- hipGraph windows of batched searches ----------------------------------
+// The launches of a window of SYNC_EVERY iterations of a batch depend only
+// on the layout of the call's device memory (its base address and the data
+// sets' shapes), the options and the window (first iteration, length, band
+// slots per iteration).  With opts.graph the window is captured into a graph
+// once and replayed by later calls whose memory has the same address and
+// layout (a caller's workspace, or a repeated allocation at the same
+// address); every graph is a chain of kernel nodes (the buffers are set by
+// fill kernels outside the windows, never by memset nodes).
+struct GraphCache {
+  std::mutex mu;
+  std::unordered_map<uint64_t, hipGraphExec_t> execs;
+};
+GraphCache g_graphs;
+constexpr size_t GRAPH_CACHE_MAX = 4096;
+
+uint64_t mix64(uint64_t h, uint64_t v) {
+  h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+  return h * 0xff51afd7ed558ccdull;
+}
+
+uint64_t batch_layout_key(const char* base, uint64_t bytes, int32_t count, const lingam_dataset* sets,
+                          const lingam_opts& o, int refresh_every, const Plan& pl) {
+  uint64_t h = mix64(0, reinterpret_cast<uintptr_t>(base));
+  h = mix64(h, bytes);
+  h = mix64(h, (uint64_t)count);
+  for (int k = 0; k < count; ++k) {
+    h = mix64(h, (uint64_t)sets[k].p);
+    h = mix64(h, (uint64_t)(sets[k].sample_idx ? sets[k].n_idx : sets[k].n));
+    int first = k;   // the first set with the same base (bootstrap bases are staged once)
+    if (sets[k].sample_idx)
+      for (int j = 0; j < k; ++j)
+        if (sets[j].sample_idx && sets[j].X == sets[k].X) { first = j; break; }
+    h = mix64(h, (uint64_t)first * 2 + (sets[k].sample_idx ? 1 : 0));
+  }
+  const uint64_t fields[] = {(uint64_t)o.precision, (uint64_t)o.use_threshold, (uint64_t)o.max_roots,
+                             (uint64_t)o.batch_queue, (uint64_t)refresh_every, (uint64_t)pl.chunk,
+                             (uint64_t)pl.band_blocks, (uint64_t)o.band_blocks, (uint64_t)o.first_band_blocks,
+                             (uint64_t)o.x_dtype,
+                             (uint64_t)o.layout, (uint64_t)o.x_on_device};
+  for (uint64_t v : fields) h = mix64(h, v);
+  uint64_t g0, gm, bt;
+  std::memcpy(&g0, &o.gamma0, 8);
+  std::memcpy(&gm, &o.gamma_mult, 8);
+  std::memcpy(&bt, &o.band_target, 8);
+  return mix64(mix64(mix64(h, g0), gm), bt);
+}
+
+// Queue iterations [t, t + nwin) of f on its stream: replayed from the cache
+// or captured and kept when `graph` is set, launched one by one otherwise.
+void queue_window(Fit& f, int t, int nwin, bool graph, uint64_t layout_key) {
+  if (!graph) {
+    for (int q = 0; q < nwin; ++q) f.queue_iteration(t + q);
+    return;
+  }
+  const uint64_t key = mix64(mix64(mix64(layout_key, (uint64_t)t), (uint64_t)nwin), (uint64_t)f.slots);
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_graphs.mu);
+    auto it = g_graphs.execs.find(key);
+    if (it != g_graphs.execs.end()) exec = it->second;
+  }
+  if (!exec) {
+    HIPCHK(hipStreamBeginCapture(f.s, hipStreamCaptureModeThreadLocal));
+    hipGraph_t g = nullptr;
+    try {
+      for (int q = 0; q < nwin; ++q) f.queue_iteration(t + q);
+    } catch (...) {
+      (void)hipStreamEndCapture(f.s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(f.s, &g));
+    const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) throw HipFail{e, "hipGraphInstantiate", __LINE__};
+    std::lock_guard<std::mutex> lk(g_graphs.mu);
+    if (g_graphs.execs.size() >= GRAPH_CACHE_MAX) {
+      for (auto& kv : g_graphs.execs) (void)hipGraphExecDestroy(kv.second);
+      g_graphs.execs.clear();
+    }
+    g_graphs.execs[key] = exec;
+  }
+  HIPCHK(hipGraphLaunch(exec, f.s));
+}
+
+lingam_status validate_batch(int32_t count, const lingam_dataset* sets, const lingam_opts& o,
+                             const lingam_result* outs) {
+  if (count < 1 || !sets) return fail(LINGAM_E_INVALID, "empty batch or NULL arrays");
+  if (count > 65535) return fail(LINGAM_E_INVALID, "at most 65535 data sets per batch");
+  lingam_status st = validate_opts(o);
+  if (st != LINGAM_OK) return st;
+  if (o.forced_len > 0 || o.record_M_iters > 0 || o.estimate_B)
+    return fail(LINGAM_E_UNSUPPORTED, "forced_order, record_M_iters and estimate_B are not available in batches");
+  for (int k = 0; k < count; ++k) {
+    const lingam_dataset& ds = sets[k];
+    if (!ds.X) return fail(LINGAM_E_INVALID, "data set with X == NULL");
+    if (outs && !outs[k].order) return fail(LINGAM_E_INVALID, "result->order is NULL");
+    const int64_t nk = ds.sample_idx ? ds.n_idx : ds.n;
+    st = validate_shape(nk, ds.p);
+    if (st != LINGAM_OK) return st;
+    if (ds.sample_idx) {
+      if (ds.n < 1) return fail(LINGAM_E_INVALID, "bootstrap base with n < 1");
+      if (o.x_dtype != 0 || o.layout != LINGAM_LAYOUT_VAR_MAJOR)
+        return fail(LINGAM_E_UNSUPPORTED, "bootstrap data sets need a binary64 p x n base");
+      for (int64_t i = 0; i < ds.n_idx; ++i)
+        if (ds.sample_idx[i] < 0 || ds.sample_idx[i] >= ds.n)
+          return fail(LINGAM_E_INVALID, "bootstrap sample index out of range");
+    }
+  }
+  return LINGAM_OK;
+}
+
+Plan batch_plan(int32_t count, const lingam_dataset* sets, const lingam_opts& o) {
+  int64_t n_max = 0;
+  for (int k = 0; k < count; ++k) n_max = std::max(n_max, sets[k].sample_idx ? sets[k].n_idx : sets[k].n);
+  return make_plan(n_max, o, false);  // the chunk length is the same for every data set
+}
+
 }  // namespace
+
+namespace lingam {
+lingam_status fit_order_in_block(const void* X, int64_t n, int64_t p, const lingam_opts* opts,
+                                 lingam_result* out, const FixedBlock& block) {
+  lingam_opts o;
+  if (opts) o = *opts; else lingam_opts_default(&o);
+  return fit_single(X, n, p, o, out, &block);
+}
+void set_last_error(const char* msg) { g_last_error = msg; }
+}  // namespace lingam
 
 extern "C" {
 
@@ -485,6 +935,7 @@ void lingam_opts_default(lingam_opts* o) {
   o->chunk_samples = 0;
   o->stream = nullptr;
   o->profile = 0;
+  o->batch_queue = 1;
 }
 
 const char* lingam_status_string(lingam_status s) {
@@ -507,122 +958,52 @@ uint64_t lingam_workspace_size(int64_t n, int64_t p, const lingam_opts* o) {
   lingam_opts_default(&def);
   const lingam_opts& op = o ? *o : def;
   if (n < 2 || p < 1) return 0;
-  const Plan pl = make_plan(n, op, true);
-  const uint64_t ldz = (uint64_t)round_up(n, SUB);
-  const uint64_t P = (uint64_t)p, pp = P * P;
-  uint64_t b = 0;
-  b += 2 * P * ldz * 8;                 // Z
-  b += 2 * pp * 8 + 5 * P * 4;          // Sigma, idx, ord, perm
-  b += P * ENT_SEGS * 16;               // entropy sums of the updated rows
-  b += pp * 8 + pp;                     // M, pend
-  b += (uint64_t)pl.nchunk * pp * 32;   // partials
-  b += 4 * P * 8 + 2 * P;               // H, S, stats, alive/complete
-  b += 16 * pp * 8 + 2 * P * 8;         // split-Gram partials, row scales
-  b += pp * (8 + 1 + 8) + P * 4;        // T, T_state, H record, order
-  b += 2 * pp * 8 + 2 * P * 8;          // rounding bounds: per test, per score record, eH, eT
-  b += (uint64_t)op.record_M_iters * pp * 8;
-  if (!op.x_on_device) b += P * (uint64_t)n * (op.x_dtype == 1 ? 4 : 8);
-  b += sizeof(Ctl) + sizeof(Dev) + 2 * PAIR_SLOTS * 8;
-  return b;
+  Arena sizing;
+  (void)layout_single(sizing, n, p, make_plan(n, op, true), op);
+  return sizing.off;
+}
+
+uint64_t lingam_workspace_size_batch(int32_t count, const lingam_dataset* sets, const lingam_opts* o) {
+  lingam_opts def;
+  lingam_opts_default(&def);
+  const lingam_opts& op = o ? *o : def;
+  if (validate_batch(count, sets, op, nullptr) != LINGAM_OK) return 0;
+  Arena sizing;
+  (void)layout_batch(sizing, count, sets, batch_plan(count, sets, op), op);
+  return sizing.off;
 }
 
 lingam_status lingam_fit_order(const void* X, int64_t n, int64_t p, const lingam_opts* opts,
                                lingam_result* out) {
-  const auto wall0 = std::chrono::steady_clock::now();
+  lingam_opts o;
+  if (opts) o = *opts; else lingam_opts_default(&o);
+  return fit_single(X, n, p, o, out, nullptr);
+}
+
+lingam_status lingam_estimate_B(const void* X, int64_t n, int64_t p, const int32_t* order,
+                                const lingam_opts* opts, double* B) {
   g_last_error.clear();
   lingam_opts o;
   if (opts) o = *opts; else lingam_opts_default(&o);
-  lingam_status st = validate(X, n, p, o, out);
-  if (st != LINGAM_OK) return st;
-  reset_result(out, p, o.record_M_iters);
-
-  Allocs al;
-  OwnedStream os;
-  PairTimer timer;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  try {
-    if (o.device >= 0) HIPCHK(hipSetDevice(o.device));
-    if (o.stream) {
-      os.s = (hipStream_t)o.stream;
-    } else {
-      HIPCHK(hipStreamCreate(&os.s));
-      os.owned = true;
-    }
-    Fit f;
-    f.timer = &timer;
-    timer.on = o.profile != 0;
-    f.o = o;
-    f.s = os.s;
-    f.refresh_every = o.cov_refresh_every >= 0 ? o.cov_refresh_every
-                      : (o.precision == LINGAM_PREC_MIXED ? REFRESH_MIXED : 1);
-    const bool mixed = o.precision == LINGAM_PREC_MIXED;
-    f.threshold = o.use_threshold != 0;
-    f.gamma0 = o.gamma0 > 0 ? o.gamma0 : 0.0;  // 0 = adaptive
-    f.gmult = o.gamma_mult > 1.0 ? o.gamma_mult : 4.0;
-    f.pl = make_plan(n, o, true);
-    f.rec = o.record_M_iters;
-    const int limit = (o.max_roots > 0 && o.max_roots < p) ? o.max_roots : (int)p;
-    f.ps = {p};
-    f.limits = {limit};
-
-    Ctl* ctl = al.get<Ctl>(1);
-    Dev d = alloc_set(al, n, p, f.pl, o, mixed, ctl);
-    d.limit = limit;
-    if (!o.x_on_device) {
-      const size_t bytes = (size_t)p * (size_t)n * (o.x_dtype == 1 ? 4 : 8);
-      void* xb = al.get<uint8_t>(bytes);
-      HIPCHK(hipMemcpyAsync(xb, X, bytes, hipMemcpyHostToDevice, f.s));
-      d.X = xb;
-    } else {
-      d.X = X;
-    }
-    Dev* dd = al.get<Dev>(1);
-    HIPCHK(hipMemcpyAsync(dd, &d, sizeof(Dev), hipMemcpyHostToDevice, f.s));
-    std::vector<int32_t> iota((size_t)p);
-    for (int64_t k = 0; k < p; ++k) iota[(size_t)k] = (int32_t)k;
-    init_set(d, o, limit, f.s, iota);
-    Ctl c0;
-    std::memset(&c0, 0, sizeof(c0));
-    c0.halt_iter = -1;
-    c0.root = -1;
-    c0.bad_i = c0.bad_j = -1;
-    HIPCHK(hipMemcpyAsync(ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, f.s));
-    HIPCHK(hipStreamSynchronize(f.s));  // host temporaries (d, iota, c0) are no longer needed
-
-    f.b.dd = dd;
-    f.b.count = 1;
-    f.b.one = d;
-    f.b.p_max = (int)p;
-    f.b.n_max = n;
-    f.b.nchunk_max = d.nchunk;
-    f.b.gram_slices_max = GRAM_SLICES_MAX;
-    f.b.mixed = mixed ? 1 : 0;
-
-    HIPCHK(hipEventCreate(&ev0));
-    HIPCHK(hipEventCreate(&ev1));
-    HIPCHK(hipEventRecord(ev0, f.s));
-    // a1 + a2: normalise once, covariance once (Alg. 3)
-    HIPCHK(launch_standardize(f.b, f.s));
-    HIPCHK(launch_gram(f.b, 0, 0, f.s));
-    Ctl c = f.drive_one(ctl, 0, limit, (int)p);
-    HIPCHK(hipEventRecord(ev1, f.s));
-    copy_results(d, c, n, out, f.s);
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) out->seconds_device = ms * 1e-3;
-    if (timer.on) {
-      out->seconds_pair_kernel = timer.total_seconds();
-      out->pair_kernel_launches = timer.launches;
-    }
-    st = (lingam_status)out->status;
-    if (st != LINGAM_OK) set_error_text(st, out);
-  } catch (const HipFail& e) {
-    st = status_from(e);
-    out->status = st;
+  if (!order || !B) return fail(LINGAM_E_INVALID, "order or B is NULL");
+  if (p < 1 || p > B_MAX_P) return fail(LINGAM_E_INVALID, "estimate_B supports 1 <= p <= 8000");
+  std::vector<char> seen((size_t)p, 0);
+  for (int64_t k = 0; k < p; ++k) {
+    const int32_t v = order[k];
+    if (v < 0 || v >= p || seen[(size_t)v]) return fail(LINGAM_E_INVALID, "order is not a permutation");
+    seen[(size_t)v] = 1;
   }
-  if (ev0) (void)hipEventDestroy(ev0);
-  if (ev1) (void)hipEventDestroy(ev1);
-  out->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
-  return st;
+  o.estimate_B = 1;
+  o.max_roots = 0;
+  o.forced_len = 0;
+  o.forced_order = nullptr;
+  o.record_M_iters = 0;
+  std::vector<int32_t> ord((size_t)p);
+  lingam_result res;
+  std::memset(&res, 0, sizeof(res));
+  res.order = ord.data();
+  res.B = B;
+  return fit_single(X, n, p, o, &res, nullptr, order);
 }
 
 lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, const lingam_opts* opts,
@@ -631,36 +1012,27 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
   g_last_error.clear();
   lingam_opts o;
   if (opts) o = *opts; else lingam_opts_default(&o);
-  if (count < 1 || !sets || !outs) return fail(LINGAM_E_INVALID, "empty batch or NULL arrays");
-  if (count > 65535) return fail(LINGAM_E_INVALID, "at most 65535 data sets per batch");
-  lingam_status st = validate_opts(o);
+  if (!outs) return fail(LINGAM_E_INVALID, "empty batch or NULL arrays");
+  lingam_status st = validate_batch(count, sets, o, outs);
   if (st != LINGAM_OK) return st;
-  if (o.forced_len > 0 || o.record_M_iters > 0)
-    return fail(LINGAM_E_UNSUPPORTED, "forced_order and record_M_iters are not available in batches");
-  for (int k = 0; k < count; ++k) {
-    const lingam_dataset& ds = sets[k];
-    if (!ds.X) return fail(LINGAM_E_INVALID, "data set with X == NULL");
-    if (!outs[k].order) return fail(LINGAM_E_INVALID, "result->order is NULL");
-    const int64_t nk = ds.sample_idx ? ds.n_idx : ds.n;
-    st = validate_shape(nk, ds.p);
-    if (st != LINGAM_OK) return st;
-    if (ds.sample_idx) {
-      if (ds.n < 1) return fail(LINGAM_E_INVALID, "bootstrap base with n < 1");
-      if (o.x_dtype != 0 || o.layout != LINGAM_LAYOUT_VAR_MAJOR)
-        return fail(LINGAM_E_UNSUPPORTED, "bootstrap data sets need a binary64 p x n base");
-      for (int64_t i = 0; i < ds.n_idx; ++i)
-        if (ds.sample_idx[i] < 0 || ds.sample_idx[i] >= ds.n)
-          return fail(LINGAM_E_INVALID, "bootstrap sample index out of range");
-    }
-  }
   for (int k = 0; k < count; ++k) reset_result(&outs[k], sets[k].p, 0);
 
-  Allocs al;
+  const Plan pl = batch_plan(count, sets, o);
+  Arena sizing;
+  (void)layout_batch(sizing, count, sets, pl, o);
+  const uint64_t need = sizing.off;
+
+  OwnedMem own;
   OwnedStream os;
   PairTimer timer;
+  DeviceGuard dg;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   try {
-    if (o.device >= 0) HIPCHK(hipSetDevice(o.device));
+    dg.set(o.device);
+    Arena ar;
+    st = acquire(need, o, own, ar);
+    if (st != LINGAM_OK) return st;
+    BatchLayout L = layout_batch(ar, count, sets, pl, o);
     if (o.stream) {
       os.s = (hipStream_t)o.stream;
     } else {
@@ -673,23 +1045,19 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
     f.o = o;
     f.s = os.s;
     f.refresh_every = o.cov_refresh_every >= 0 ? o.cov_refresh_every
-                      : (o.precision == LINGAM_PREC_MIXED ? REFRESH_MIXED : 1);
-    const bool mixed = o.precision == LINGAM_PREC_MIXED;
+                      : (o.precision != LINGAM_PREC_FP64 ? REFRESH_MIXED : 1);
+    const bool mixed = o.precision != LINGAM_PREC_FP64;
     f.threshold = o.use_threshold != 0;
     f.gamma0 = o.gamma0 > 0 ? o.gamma0 : 0.0;
     f.gmult = o.gamma_mult > 1.0 ? o.gamma_mult : 4.0;
+    f.pl = pl;
     int64_t p_max = 0, n_max = 0;
     for (int k = 0; k < count; ++k) {
       p_max = std::max(p_max, sets[k].p);
       n_max = std::max(n_max, sets[k].sample_idx ? sets[k].n_idx : sets[k].n);
     }
-    f.pl = make_plan(n_max, o, false);  // the chunk length is the same for every data set
-    Ctl* ctls = al.get<Ctl>((size_t)count);
-    std::vector<Dev> devs((size_t)count);
     f.ps.resize((size_t)count);
     f.limits.resize((size_t)count);
-    // bases of bootstrap sets are uploaded once each
-    std::vector<std::pair<const void*, const double*>> bases;
     std::vector<int32_t> iota((size_t)p_max);
     for (int64_t k = 0; k < p_max; ++k) iota[(size_t)k] = (int32_t)k;
     int nchunk_max = 1;
@@ -697,43 +1065,27 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
       const lingam_dataset& ds = sets[k];
       const int64_t nk = ds.sample_idx ? ds.n_idx : ds.n, pk = ds.p;
       const int limit = (o.max_roots > 0 && o.max_roots < pk) ? o.max_roots : (int)pk;
-      Dev d = alloc_set(al, nk, pk, f.pl, o, mixed, ctls + k);
+      Dev& d = L.devs[(size_t)k];
       d.limit = limit;
       if (ds.sample_idx) {
-        const double* base = nullptr;
-        for (auto& bp : bases) if (bp.first == ds.X) base = bp.second;
-        if (!base) {
-          if (o.x_on_device) {
-            base = (const double*)ds.X;
-          } else {
-            double* xb = al.get<double>((size_t)pk * (size_t)ds.n);
-            HIPCHK(hipMemcpyAsync(xb, ds.X, sizeof(double) * pk * ds.n, hipMemcpyHostToDevice, f.s));
-            base = xb;
-          }
-          bases.push_back({ds.X, base});
-        }
-        int64_t* idx_dev = al.get<int64_t>((size_t)ds.n_idx);
-        HIPCHK(hipMemcpyAsync(idx_dev, ds.sample_idx, sizeof(int64_t) * ds.n_idx, hipMemcpyHostToDevice, f.s));
-        double* xg = al.get<double>((size_t)pk * (size_t)nk);
-        HIPCHK(launch_gather(base, ds.n, pk, idx_dev, nk, xg, f.s));
-        d.X = xg;
-        d.x_dtype = 0;
-        d.layout = 0;
-      } else if (!o.x_on_device) {
-        const size_t bytes = (size_t)pk * (size_t)nk * (o.x_dtype == 1 ? 4 : 8);
-        void* xb = al.get<uint8_t>(bytes);
-        HIPCHK(hipMemcpyAsync(xb, ds.X, bytes, hipMemcpyHostToDevice, f.s));
-        d.X = xb;
-      } else {
-        d.X = ds.X;
+        if (L.base_upload[(size_t)k])
+          HIPCHK(hipMemcpyAsync(const_cast<double*>(L.base[(size_t)k]), ds.X, sizeof(double) * pk * ds.n,
+                                hipMemcpyHostToDevice, f.s));
+        HIPCHK(hipMemcpyAsync(L.idx[(size_t)k], ds.sample_idx, sizeof(int64_t) * ds.n_idx,
+                              hipMemcpyHostToDevice, f.s));
+        HIPCHK(launch_gather(L.base[(size_t)k], ds.n, pk, L.idx[(size_t)k], nk,
+                             const_cast<double*>(static_cast<const double*>(d.X)), f.s));
+      } else if (L.xb[(size_t)k]) {
+        HIPCHK(hipMemcpyAsync(L.xb[(size_t)k], ds.X, x_bytes(nk, pk, o), hipMemcpyHostToDevice, f.s));
       }
       init_set(d, o, limit, f.s, iota);
-      devs[(size_t)k] = d;
       f.ps[(size_t)k] = pk;
       f.limits[(size_t)k] = limit;
       nchunk_max = std::max(nchunk_max, d.nchunk);
     }
-    Dev* dd = al.get<Dev>((size_t)count);
+    Ctl* ctls = L.ctls;
+    Dev* dd = L.dd;
+    std::vector<Dev>& devs = L.devs;
     HIPCHK(hipMemcpyAsync(dd, devs.data(), sizeof(Dev) * count, hipMemcpyHostToDevice, f.s));
     std::vector<Ctl> c0((size_t)count);
     std::memset(c0.data(), 0, sizeof(Ctl) * count);
@@ -752,6 +1104,8 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
     f.b.nchunk_max = nchunk_max;
     f.b.gram_slices_max = GRAM_SLICES_MAX;
     f.b.mixed = mixed ? 1 : 0;
+    f.b.store32 = o.precision == LINGAM_PREC_FP32_STORAGE ? 1 : 0;
+    f.b.queue = o.batch_queue ? 1 : 0;
     int limit_max = 0;
     for (int l : f.limits) limit_max = std::max(limit_max, l);
 
@@ -763,8 +1117,12 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
     // every data set steps through its iterations together; one that halts
     // (not enough threshold rounds queued, or an error) sits out from then on
     std::vector<Ctl> cs((size_t)count);
+    const bool graph = o.graph != 0 && !timer.on;
+    const uint64_t lkey = graph ? batch_layout_key(ar.base, need, count, sets, o, f.refresh_every, pl) : 0;
     for (int t = 0; t < limit_max;) {
-      for (int q = 0; q < SYNC_EVERY && t < limit_max; ++q, ++t) f.queue_iteration(t);
+      const int nwin = std::min(SYNC_EVERY, limit_max - t);
+      queue_window(f, t, nwin, graph, lkey);
+      t += nwin;
       HIPCHK(hipMemcpyAsync(cs.data(), ctls, sizeof(Ctl) * count, hipMemcpyDeviceToHost, f.s));
       HIPCHK(hipStreamSynchronize(f.s));
       int wb = 0;
@@ -807,6 +1165,12 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
     }
   } catch (const HipFail& e) {
     st = status_from(e);
+    for (int k = 0; k < count; ++k) outs[k].status = st;
+  } catch (const NoMem& e) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "workspace layout needs %llu bytes, %llu available",
+                  (unsigned long long)e.need, (unsigned long long)e.have);
+    st = fail(LINGAM_E_NOMEM, buf);
     for (int k = 0; k < count; ++k) outs[k].status = st;
   }
   if (ev0) (void)hipEventDestroy(ev0);

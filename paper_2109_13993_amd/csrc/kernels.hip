@@ -138,12 +138,20 @@ __device__ __forceinline__ void terms_mixed(float x, float ca, float cg, float& 
 //   2 k1 |E1 - beta| dE1 + 3 k1 dE1^2 + 2 k2 |E2| dE2 + 3 k2 dE2^2
 // (E1, E2 the computed means; the factor 3 absorbs using them in place of the
 // exact ones).
-__device__ __forceinline__ double happ_err_mixed(double s_lc, double s_g, double n) {
+// d_in (in units of u32) adds an error of the arguments themselves to both
+// moments: with binary32 rows (FP32 storage) a residual u = s (z_v - b z_w)
+// is formed by one binary32 fma from rows stored to u32 and b rounded to
+// binary32, which moves it by at most u32 s (|z_v| + 2 |z_w|) beyond its own
+// rounding; both term derivatives are at most 1 in magnitude and the rows
+// have unit variance (mean |z| <= 1), so each moment moves by at most
+// 3 s u32 more: d_in = 3 s.  (0 for a variable's own entropy and for
+// residuals formed in binary64.)
+__device__ __forceinline__ double happ_err_mixed(double s_lc, double s_g, double n, double d_in = 0.0) {
   constexpr double U32 = 5.9604644775390625e-08;
   const double E1 = s_lc / n - LN2;
   const double E2 = s_g / n;
-  const double d1 = U32 * (32.0 * (s_lc / n) + 11.6);
-  const double d2 = U32 * 25.4;
+  const double d1 = U32 * (32.0 * (s_lc / n) + 11.6 + d_in);
+  const double d2 = U32 * (25.4 + d_in);
   return 2.0 * K1 * fabs(E1 - BETA) * d1 + 3.0 * K1 * d1 * d1 + 2.0 * K2 * fabs(E2) * d2 +
          3.0 * K2 * d2 * d2;
 }
@@ -161,8 +169,8 @@ __device__ __forceinline__ double happ_from_sums(double s_lc, double s_g, double
 // ============================================================================
 // a1: NormalizeData
 // ============================================================================
-template <typename T, int LAYOUT>
-__device__ void standardize_row(const T* __restrict__ X, int64_t n, int p, int i, double* __restrict__ Z,
+template <typename T, int LAYOUT, typename S>
+__device__ void standardize_row(const T* __restrict__ X, int64_t n, int p, int i, S* __restrict__ Z,
                                 int64_t ldz, Ctl* ctl, double* stats) {
   __shared__ double sh[4];
   __shared__ int shi[4];
@@ -196,8 +204,8 @@ __device__ void standardize_row(const T* __restrict__ X, int64_t n, int p, int i
     return;
   }
   const double sd = sqrt(var);
-  double* z = Z + (int64_t)i * ldz;
-  for (int64_t k = threadIdx.x; k < ldz; k += 256) z[k] = k < n ? (load(k) - mean) / sd : 0.0;
+  S* z = Z + (int64_t)i * ldz;
+  for (int64_t k = threadIdx.x; k < ldz; k += 256) z[k] = k < n ? (S)((load(k) - mean) / sd) : (S)0;
   if (threadIdx.x == 0 && stats) {
     stats[2 * i] = mean;
     stats[2 * i + 1] = var;
@@ -205,17 +213,26 @@ __device__ void standardize_row(const T* __restrict__ X, int64_t n, int p, int i
 }
 
 // One work-group per row (blockIdx.x) of data set blockIdx.z.
+template <typename S>
+__device__ __forceinline__ void standardize_into(const Dev& d, int i) {
+  S* Z = static_cast<S*>(d.Z[0]);
+  if (d.x_dtype == 0 && d.layout == 0)
+    standardize_row<double, 0, S>((const double*)d.X, d.n, d.p, i, Z, d.ldz, d.ctl, d.stats);
+  else if (d.x_dtype == 0)
+    standardize_row<double, 1, S>((const double*)d.X, d.n, d.p, i, Z, d.ldz, d.ctl, d.stats);
+  else if (d.layout == 0)
+    standardize_row<float, 0, S>((const float*)d.X, d.n, d.p, i, Z, d.ldz, d.ctl, d.stats);
+  else
+    standardize_row<float, 1, S>((const float*)d.X, d.n, d.p, i, Z, d.ldz, d.ctl, d.stats);
+}
+
 __device__ __forceinline__ void k_standardize_body(const Dev& d) {
   const int i = blockIdx.x;
   if (i >= d.p) return;
-  if (d.x_dtype == 0 && d.layout == 0)
-    standardize_row<double, 0>((const double*)d.X, d.n, d.p, i, d.Z[0], d.ldz, d.ctl, d.stats);
-  else if (d.x_dtype == 0)
-    standardize_row<double, 1>((const double*)d.X, d.n, d.p, i, d.Z[0], d.ldz, d.ctl, d.stats);
-  else if (d.layout == 0)
-    standardize_row<float, 0>((const float*)d.X, d.n, d.p, i, d.Z[0], d.ldz, d.ctl, d.stats);
+  if (d.store32)
+    standardize_into<float>(d, i);
   else
-    standardize_row<float, 1>((const float*)d.X, d.n, d.p, i, d.Z[0], d.ldz, d.ctl, d.stats);
+    standardize_into<double>(d, i);
 }
 
 __global__ __launch_bounds__(256) void k_standardize(const Dev* __restrict__ devs, const Dev one) {
@@ -277,10 +294,11 @@ __host__ __device__ inline int gram_slices(int r, int64_t n, int max_slices) {
 // Grid: (tiles, slices, data sets), sized for the largest data set; each
 // data set uses its own tile and slice counts (the same as when it runs
 // alone), and the surplus work-groups return.
+template <typename S>
 __device__ __forceinline__ void k_gram_partial_body(const Dev& d, int buf, int t) {
   const int r = rows_left(d, t);
   if (r < 1 || halted(d.ctl)) return;
-  const double* __restrict__ Z = d.Z[buf];
+  const S* __restrict__ Z = static_cast<const S*>(d.Z[buf]);
   const int64_t ldz = d.ldz, n = d.n;
   double* __restrict__ Gp = d.Gp;
   const int ldg = d.p;
@@ -304,17 +322,27 @@ __device__ __forceinline__ void k_gram_partial_body(const Dev& d, int buf, int t
   constexpr int PER = (GT * GK) / 256;
   const int row0 = threadIdx.x / (GK / PER), col0 = (threadIdx.x % (GK / PER)) * PER;
   const bool ra = i0 + row0 < r, rb = j0 + row0 < r;
-  const double* za = Z + (int64_t)(i0 + row0) * ldz + col0;
-  const double* zb = Z + (int64_t)(j0 + row0) * ldz + col0;
+  const S* za = Z + (int64_t)(i0 + row0) * ldz + col0;
+  const S* zb = Z + (int64_t)(j0 + row0) * ldz + col0;
   double pa[PER], pb[PER];
+  // binary32 rows are widened exactly, so the Gram is the same binary64
+  // contraction of the stored values
   auto fetch = [&](int64_t k0) {
 #pragma unroll
     for (int e = 0; e < PER; e += 2) {
-      double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
-      if (ra) va = *reinterpret_cast<const double2*>(za + k0 + e);
-      if (rb) vb = *reinterpret_cast<const double2*>(zb + k0 + e);
-      pa[e] = va.x; pa[e + 1] = va.y;
-      pb[e] = vb.x; pb[e + 1] = vb.y;
+      if constexpr (sizeof(S) == 8) {
+        double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+        if (ra) va = *reinterpret_cast<const double2*>(za + k0 + e);
+        if (rb) vb = *reinterpret_cast<const double2*>(zb + k0 + e);
+        pa[e] = va.x; pa[e + 1] = va.y;
+        pb[e] = vb.x; pb[e + 1] = vb.y;
+      } else {
+        float2 va = make_float2(0.f, 0.f), vb = make_float2(0.f, 0.f);
+        if (ra) va = *reinterpret_cast<const float2*>(za + k0 + e);
+        if (rb) vb = *reinterpret_cast<const float2*>(zb + k0 + e);
+        pa[e] = (double)va.x; pa[e + 1] = (double)va.y;
+        pb[e] = (double)vb.x; pb[e + 1] = (double)vb.y;
+      }
     }
   };
   dbl4 tot = {0.0, 0.0, 0.0, 0.0}, comp = {0.0, 0.0, 0.0, 0.0};
@@ -353,11 +381,12 @@ __device__ __forceinline__ void k_gram_partial_body(const Dev& d, int buf, int t
   }
 }
 
+template <typename S>
 __global__ __launch_bounds__(256) void k_gram_partial(const Dev* __restrict__ devs, const Dev one, int buf, int t) {
   if (devs)
-    k_gram_partial_body(devs[blockIdx.z], buf, t);
+    k_gram_partial_body<S>(devs[blockIdx.z], buf, t);
   else
-    k_gram_partial_body(one, buf, t);
+    k_gram_partial_body<S>(one, buf, t);
 }
 
 // Sum the slices in a fixed order, scale by 1/(n-1), mirror, and set the row
@@ -394,8 +423,11 @@ hipError_t launch_gram(const Batch& b, int buf, int t, hipStream_t s) {
   const int r = b.p_max - t;
   if (r < 1) return hipSuccess;
   const int nt = (r + GT - 1) / GT;
-  hipLaunchKernelGGL(k_gram_partial, dim3(nt * (nt + 1) / 2, b.gram_slices_max, b.count), dim3(256), 0, s,
-                     DEVS(b), buf, t);
+  const dim3 grid(nt * (nt + 1) / 2, b.gram_slices_max, b.count);
+  if (b.store32)
+    hipLaunchKernelGGL(k_gram_partial<float>, grid, dim3(256), 0, s, DEVS(b), buf, t);
+  else
+    hipLaunchKernelGGL(k_gram_partial<double>, grid, dim3(256), 0, s, DEVS(b), buf, t);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gram_reduce, dim3((r + 255) / 256, r, b.count), dim3(256), 0, s, DEVS(b), buf, t);
@@ -427,6 +459,26 @@ __device__ __forceinline__ void iter_init_row(const Dev& d, int t, int x, double
     d.complete[x] = 0;
     d.alive_list[x] = x;
   }
+  // Degeneracy of every pair of the row, pruned or not: a normalised
+  // residual needs 1 - b^2 > 0 (Eq. var_update), and the row update divides
+  // by sqrt(1 - b^2) for whichever variable becomes the root.  b is formed
+  // exactly as the pair kernel forms it.
+  {
+    const int buf = t & 1;
+    const double* sig = d.Sig[buf] + (int64_t)x * p;
+    const double* dsc = d.dsc[buf];
+    const double dx = dsc[x];
+    int bad = -1;
+    for (int w = threadIdx.x; w < r; w += blockDim.x) {
+      if (w == x) continue;
+      const double b = sig[w] * (dx * dsc[w]);
+      if (!(1.0 - b * b > DEGEN_EPS)) bad = w;
+    }
+    if (bad >= 0) {
+      const int32_t* idx = d.idx[buf];
+      raise_error(ctl, ST_DEGENERATE, idx[x], idx[bad]);
+    }
+  }
   if (x == 0 && threadIdx.x == 0) {
     double g = gamma0;
     if (!(g > 0.0)) {
@@ -442,6 +494,9 @@ __device__ __forceinline__ void iter_init_row(const Dev& d, int t, int x, double
     ctl->tb_next = 0;
     ctl->ntb_next = threshold ? min(d.band_k0, nb) : nb;
     ctl->iter_bands = 0;
+    ctl->arrivals = 0;
+    ctl->q_next = 0;
+    ctl->q_rows = 0;
   }
 }
 
@@ -480,7 +535,7 @@ __host__ __device__ inline int entropy_segments_of(int64_t n) {
   return (int)(s < 1 ? 1 : (s < ENT_SEGS ? s : ENT_SEGS));
 }
 
-template <bool MIXED, int NT>
+template <bool MIXED, int NT, typename S>
 __device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma0, double adapt, int threshold,
                                                int fused) {
   const int r = rows_left(d, t);
@@ -509,7 +564,7 @@ __device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma
   // the row is normalised here, once per iteration: d z is used for the
   // entropy and, when the Gram refresh gave d != 1, stored back in place for
   // the rest of the iteration
-  double* z = d.Z[buf] + (int64_t)blockIdx.x * d.ldz;
+  S* z = static_cast<S*>(d.Z[buf]) + (int64_t)blockIdx.x * d.ldz;
   const double dz = d.dsc[buf][blockIdx.x];
   const bool store = dz != 1.0;
   const int W = NT >= 1024 && n >= ENT_WIDE_N ? 1024 : 256;
@@ -523,8 +578,9 @@ __device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma
 #pragma unroll 4
         for (int c = 0; c < 32; ++c, k += W)
           if (k < n) {
-            const double zk = dz * z[k];
-            if (store) z[k] = zk;
+            // the terms see exactly the value the row then holds
+            const double zk = dz * (double)z[k];
+            if (store) z[k] = (S)zk;
             terms_mixed((float)zk, ca, cg, flc, fg);
           }
         lc += (double)flc * LN2;
@@ -533,8 +589,8 @@ __device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma
     } else {
 #pragma unroll 4
       for (int64_t k = threadIdx.x; k < n; k += W) {
-        const double zk = dz * z[k];
-        if (store) z[k] = zk;
+        const double zk = dz * (double)z[k];
+        if (store) z[k] = (S)zk;
         terms_f64(zk, lc, g);
       }
     }
@@ -547,13 +603,13 @@ __device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma
   }
 }
 
-template <bool MIXED, int NT>
+template <bool MIXED, int NT, typename S>
 __global__ __launch_bounds__(NT) void k_entropy(const Dev* __restrict__ devs, const Dev one, int t, double gamma0,
                                                 double adapt, int threshold, int fused) {
   if (devs)
-    k_entropy_body<MIXED, NT>(devs[blockIdx.z], t, gamma0, adapt, threshold, fused);
+    k_entropy_body<MIXED, NT, S>(devs[blockIdx.z], t, gamma0, adapt, threshold, fused);
   else
-    k_entropy_body<MIXED, NT>(one, t, gamma0, adapt, threshold, fused);
+    k_entropy_body<MIXED, NT, S>(one, t, gamma0, adapt, threshold, fused);
 }
 
 hipError_t launch_iter_start(const Batch& b, int t, double gamma0, double adapt, int threshold, int fused,
@@ -562,17 +618,23 @@ hipError_t launch_iter_start(const Batch& b, int t, double gamma0, double adapt,
   if (r < 2) return hipSuccess;
   const dim3 g(r, 1, b.count);
   const bool wide = b.n_max >= ENT_WIDE_N;
-  if (b.mixed && wide)
-    hipLaunchKernelGGL((k_entropy<true, 1024>), g, dim3(1024), 0, s, DEVS(b), t, gamma0, adapt, threshold,
+  if (b.store32 && wide)
+    hipLaunchKernelGGL((k_entropy<true, 1024, float>), g, dim3(1024), 0, s, DEVS(b), t, gamma0, adapt, threshold,
+                       fused);
+  else if (b.store32)
+    hipLaunchKernelGGL((k_entropy<true, 256, float>), g, dim3(256), 0, s, DEVS(b), t, gamma0, adapt, threshold,
+                       fused);
+  else if (b.mixed && wide)
+    hipLaunchKernelGGL((k_entropy<true, 1024, double>), g, dim3(1024), 0, s, DEVS(b), t, gamma0, adapt, threshold,
                        fused);
   else if (b.mixed)
-    hipLaunchKernelGGL((k_entropy<true, 256>), g, dim3(256), 0, s, DEVS(b), t, gamma0, adapt, threshold,
+    hipLaunchKernelGGL((k_entropy<true, 256, double>), g, dim3(256), 0, s, DEVS(b), t, gamma0, adapt, threshold,
                        fused);
   else if (wide)
-    hipLaunchKernelGGL((k_entropy<false, 1024>), g, dim3(1024), 0, s, DEVS(b), t, gamma0, adapt, threshold,
-                       fused);
+    hipLaunchKernelGGL((k_entropy<false, 1024, double>), g, dim3(1024), 0, s, DEVS(b), t, gamma0, adapt,
+                       threshold, fused);
   else
-    hipLaunchKernelGGL((k_entropy<false, 256>), g, dim3(256), 0, s, DEVS(b), t, gamma0, adapt, threshold,
+    hipLaunchKernelGGL((k_entropy<false, 256, double>), g, dim3(256), 0, s, DEVS(b), t, gamma0, adapt, threshold,
                        fused);
   return hipGetLastError();
 }
@@ -626,12 +688,22 @@ constexpr int log2_of() { return NV <= 1 ? 0 : 1 + log2_of<NV / 2>(); }
 // LDS PS samples at a time, double-buffered: the loads of the next stage are
 // issued before the current stage is computed, so one barrier per stage
 // suffices and the load latency hides behind the arithmetic.
-template <bool MIXED, int RG, int TPW, int PS>
-__device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a) {
+// S is the stored element type: binary64 rows (FP64 and MIXED), or binary32
+// rows (FP32 storage, MIXED terms), whose residuals are formed by binary32
+// fused multiply-adds with b rounded to binary32.
+//
+// One item of a band of data set d: row group g of the alive list against
+// target block tb0 + tb over sample chunk `chunk` (item = g + nrg (tb + ntb
+// chunk)).  The work-group's waves count the pairs they evaluate and
+// compute in n_eval / n_comp.
+template <bool MIXED, int RG, int TPW, int PS, typename S>
+__device__ __forceinline__ void pair_item(const Dev& d, int t, const BandArgs& a, int item, int m, int tb0,
+                                          int ntb, unsigned& n_eval, unsigned& n_comp) {
+  static_assert(MIXED || sizeof(S) == 8, "binary32 rows take the mixed-precision terms");
+  constexpr bool ROW32 = sizeof(S) == 4;
   const int r = rows_left(d, t), p = d.p;
-  if (r < 2) return;
   const int buf = t & 1;
-  const double* __restrict__ Z = d.Z[buf];
+  const S* __restrict__ Z = static_cast<const S*>(d.Z[buf]);
   const int64_t ldz = d.ldz, n = d.n;
   const double* __restrict__ Sig = d.Sig[buf];
   const double* __restrict__ dsc = d.dsc[buf];
@@ -642,43 +714,20 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
   uint8_t* __restrict__ pend = d.pend;
   const int32_t* __restrict__ idx = d.idx[buf];
   Ctl* ctl = d.ctl;
-  const int nchunk = d.nchunk;
   constexpr int WPR = TB / TPW;     // waves per row
   constexpr int NW = RG * WPR;      // waves per work-group
   constexpr int SPL = PS / 64;      // samples per lane and stage
   constexpr int NT = 64 * NW;       // threads
-  constexpr int NSTG = TB * PS / 2 / NT;  // double2 of the target rows each thread stages
-  static_assert(NSTG >= 1 && NSTG * NT == TB * PS / 2, "stage must split evenly over the threads");
-  __shared__ double lds[2][TB][PS];  // the 8 rows of target block B, two stages
+  constexpr int EV = 16 / (int)sizeof(S);  // elements per 16-byte staging load
+  using V = typename std::conditional<ROW32, float4, double2>::type;
+  constexpr int NSTG = TB * PS / EV / NT;  // 16-byte loads of the target rows each thread stages
+  static_assert(NSTG >= 1 && NSTG * NT == TB * PS / EV, "stage must split evenly over the threads");
+  __shared__ S lds[2][TB][PS];  // the 8 rows of target block B, two stages
   __shared__ double s_sc[NW][TPW];   // per-pair scale s = 1/sqrt(1 - b^2)
   __shared__ uint32_t s_mask[NW];
-  __shared__ int s_stop, s_m, s_tb0, s_ntb;
-  // the stop decision, the alive count and the band are read once and
-  // shared, so the whole work-group decides together
-  if (threadIdx.x == 0) {
-    s_stop = halted(ctl) || ctl->done;
-    s_m = ctl->n_alive;
-    s_tb0 = ctl->tb_next;
-    s_ntb = ctl->ntb_next;
-  }
-  __syncthreads();
-  const int m = s_m;
-  if (s_stop) return;
-  const int tb0 = s_tb0, ntb = s_ntb;
-  // items (row group, target block, chunk) that exist for this alive count;
-  // the grid is bounded and each work-group walks its share of them.  Work-
-  // groups are dealt round-robin over the 8 XCDs, so each XCD takes one
-  // contiguous eighth of the items (same chunk and target block, different
-  // row groups) and its work-groups share the XCD's L2.
-  const int nrg = (m + RG - 1) / RG;
-  const int items = nrg * ntb * nchunk;
-  const int xcd = blockIdx.x % 8, per_xcd = gridDim.x / 8;
-  const int ipx = (items + 7) / 8;
-  const int lo = xcd * ipx, hi = min(items, lo + ipx);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int lane = threadIdx.x % 64;
-  unsigned n_eval = 0, n_comp = 0;  // pairs this wave evaluated / computed
-  for (int item = lo + (int)(blockIdx.x / 8); item < hi; item += per_xcd) {
+  const int nrg = (m + RG - 1) / RG;
   const int g = item % nrg;
   const int tb = (item / nrg) % ntb;
   const int chunk = item / (nrg * ntb);
@@ -708,13 +757,14 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
   for (int w = 0; w < NW; ++w) n_act += s_mask[w] ? 1 : 0;
   if (n_act == 0) {  // nothing in this item for any wave (uniform)
     __syncthreads();
-    continue;
+    return;
   }
 
   // per-pair regression coefficient b (correlation of the normalised rows)
   // and scale s = 1/sqrt(1 - b^2) (Eq. var_update); s waits in LDS for the
   // epilogue so it holds no registers during the sample loop
   double bj[TPW];
+  float bf[TPW];  // b rounded to binary32 (binary32 rows)
   float ca[TPW], cg[TPW];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
@@ -734,6 +784,7 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
       }
     }
     if (lane == j) s_sc[wave][j] = sj;
+    bf[j] = (float)bj[j];
     ca[j] = (float)(-2.0 * 1.4426950408889634074 * sj);
     cg[j] = (float)(-0.5 * 1.4426950408889634074 * sj * sj);
   }
@@ -741,19 +792,19 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
   const int64_t k0 = (int64_t)chunk * a.chunk;
   const int64_t kend = min(n, k0 + (int64_t)a.chunk);
   const int nst = (int)((kend - k0 + PS - 1) / PS);
-  const double* zrow = Z + (int64_t)(mask ? v : 0) * ldz;
+  const S* zrow = Z + (int64_t)(mask ? v : 0) * ldz;
   // this thread's share of the staged target rows (a target position past
   // the last variable, var >= r, is read from row r - 1, and its pairs are
   // never kept)
-  const double* srow[NSTG];
+  const S* srow[NSTG];
 #pragma unroll
   for (int i = 0; i < NSTG; ++i) {
     const int e = i * NT + (int)threadIdx.x;
-    const int var = B * TB + e / (PS / 2);
-    srow[i] = Z + (int64_t)min(var, r - 1) * ldz + 2 * (e % (PS / 2));
+    const int var = B * TB + e / (PS / EV);
+    srow[i] = Z + (int64_t)min(var, r - 1) * ldz + EV * (e % (PS / EV));
   }
-  double2 stg[NSTG];
-  double zn[SPL];
+  V stg[NSTG];
+  S zn[SPL];
   // global loads of one stage into registers.  A stage starts at a multiple
   // of SUB below n, and PS divides SUB, so the whole stage lies inside the
   // row's zero-padded stride ldz = n rounded up to SUB: the loads need no
@@ -761,7 +812,7 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
   static_assert(SUB % PS == 0, "a stage must end inside the padded row");
   auto load_stage = [&](int64_t ks) {
 #pragma unroll
-    for (int i = 0; i < NSTG; ++i) stg[i] = *reinterpret_cast<const double2*>(srow[i] + ks);
+    for (int i = 0; i < NSTG; ++i) stg[i] = *reinterpret_cast<const V*>(srow[i] + ks);
 #pragma unroll
     for (int i = 0; i < SPL; ++i) zn[i] = zrow[ks + i * 64 + lane];
   };
@@ -778,15 +829,18 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
   for (int st = 0; st < nst; ++st) {
     const int64_t ks = k0 + (int64_t)st * PS;
     const int cnt = (int)min((int64_t)PS, kend - ks);
-    double (*buf)[PS] = lds[st & 1];
+    S (*buf)[PS] = lds[st & 1];
 #pragma unroll
     for (int i = 0; i < NSTG; ++i) {
       const int e = i * NT + (int)threadIdx.x;
-      const int row = e / (PS / 2), c2 = e % (PS / 2);
+      const int row = e / (PS / EV), c2 = e % (PS / EV);
       // element-wise, so that stg stays in registers
-      *reinterpret_cast<double2*>(&buf[row][2 * c2]) = make_double2(stg[i].x, stg[i].y);
+      if constexpr (ROW32)
+        *reinterpret_cast<float4*>(&buf[row][EV * c2]) = make_float4(stg[i].x, stg[i].y, stg[i].z, stg[i].w);
+      else
+        *reinterpret_cast<double2*>(&buf[row][EV * c2]) = make_double2(stg[i].x, stg[i].y);
     }
-    double zv[SPL];
+    S zv[SPL];
 #pragma unroll
     for (int i = 0; i < SPL; ++i) zv[i] = zn[i];
     // buf is complete, and every wave has finished the stage that last used
@@ -800,18 +854,25 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
         if (k < cnt) {
 #pragma unroll
           for (int j = 0; j < TPW; ++j) {
-            const double zw = buf[j0 + j][k];
-            const double rv = __builtin_fma(-bj[j], zw, zv[i]);  // r_v^(w) / s
-            const double rw = __builtin_fma(-bj[j], zv[i], zw);  // r_w^(v) / s
-            if constexpr (MIXED) {
-              terms_mixed((float)rv, ca[j], cg[j], acc[j][0], acc[j][1]);
-              terms_mixed((float)rw, ca[j], cg[j], acc[j][2], acc[j][3]);
+            const S zw = buf[j0 + j][k];
+            if constexpr (ROW32) {
+              const float rv = __builtin_fmaf(-bf[j], zw, zv[i]);  // r_v^(w) / s
+              const float rw = __builtin_fmaf(-bf[j], zv[i], zw);  // r_w^(v) / s
+              terms_mixed(rv, ca[j], cg[j], acc[j][0], acc[j][1]);
+              terms_mixed(rw, ca[j], cg[j], acc[j][2], acc[j][3]);
             } else {
-              const double sj = s_sc[wave][j];
-              double t0 = acc[j][0], t1 = acc[j][1], t2 = acc[j][2], t3 = acc[j][3];
-              terms_f64(sj * rv, t0, t1);
-              terms_f64(sj * rw, t2, t3);
-              acc[j][0] = t0; acc[j][1] = t1; acc[j][2] = t2; acc[j][3] = t3;
+              const double rv = __builtin_fma(-bj[j], zw, zv[i]);  // r_v^(w) / s
+              const double rw = __builtin_fma(-bj[j], zv[i], zw);  // r_w^(v) / s
+              if constexpr (MIXED) {
+                terms_mixed((float)rv, ca[j], cg[j], acc[j][0], acc[j][1]);
+                terms_mixed((float)rw, ca[j], cg[j], acc[j][2], acc[j][3]);
+              } else {
+                const double sj = s_sc[wave][j];
+                double t0 = acc[j][0], t1 = acc[j][1], t2 = acc[j][2], t3 = acc[j][3];
+                terms_f64(sj * rv, t0, t1);
+                terms_f64(sj * rw, t2, t3);
+                acc[j][0] = t0; acc[j][1] = t1; acc[j][2] = t2; acc[j][3] = t3;
+              }
             }
           }
         }
@@ -855,7 +916,42 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
     n_comp += TPW;
   }
   __syncthreads();  // s_mask, s_sc and lds are reused by the next item
+}
+
+// A band of one data set (blockIdx.z of a grid-z launch, or the only one):
+// the grid is bounded and each work-group walks its share of the items.
+// Work-groups are dealt round-robin over the 8 XCDs, so each XCD takes one
+// contiguous eighth of the items (same chunk and target block, different
+// row groups) and its work-groups share the XCD's L2.
+template <bool MIXED, int RG, int TPW, int PS, typename S>
+__device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a) {
+  constexpr int NW = RG * (TB / TPW);
+  const int r = rows_left(d, t);
+  if (r < 2) return;
+  Ctl* ctl = d.ctl;
+  __shared__ int s_stop, s_m, s_tb0, s_ntb;
+  // the stop decision, the alive count and the band are read once and
+  // shared, so the whole work-group decides together
+  if (threadIdx.x == 0) {
+    s_stop = halted(ctl) || ctl->done;
+    s_m = ctl->n_alive;
+    s_tb0 = ctl->tb_next;
+    s_ntb = ctl->ntb_next;
   }
+  __syncthreads();
+  const int m = s_m;
+  if (s_stop) return;
+  const int tb0 = s_tb0, ntb = s_ntb;
+  const int nrg = (m + RG - 1) / RG;
+  const int items = nrg * ntb * d.nchunk;
+  const int xcd = blockIdx.x % 8, per_xcd = gridDim.x / 8;
+  const int ipx = (items + 7) / 8;
+  const int lo = xcd * ipx, hi = min(items, lo + ipx);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int lane = threadIdx.x % 64;
+  unsigned n_eval = 0, n_comp = 0;  // pairs this wave evaluated / computed
+  for (int item = lo + (int)(blockIdx.x / 8); item < hi; item += per_xcd)
+    pair_item<MIXED, RG, TPW, PS, S>(d, t, a, item, m, tb0, ntb, n_eval, n_comp);
   // one add per wave, on addresses spread over the slots
   if (lane == 0 && n_comp) {
     const int slot = (int)((blockIdx.x * NW + wave) % PAIR_SLOTS);
@@ -864,15 +960,111 @@ __device__ __forceinline__ void k_pair_band_body(const Dev& d, int t, BandArgs a
   }
 }
 
+// Items of a batch's data set at the current band (0 when it has no band
+// running: finished, halted, or its iteration decided).
+template <int RG>
+__device__ __forceinline__ int band_items(const Dev& d, int t) {
+  const Ctl* c = d.ctl;
+  if (rows_left(d, t) < 2 || halted(c) || c->done) return 0;
+  return (c->n_alive + RG - 1) / RG * c->ntb_next * d.nchunk;
+}
+
+// Device work queue over the data sets of a batch.  The grid is persistent
+// (about the work-groups the device holds at once) and not tied to any data
+// set: a work-group claims QCLAIM items of one data set at a time from that
+// set's claim counter (Ctl::q_next), and when its set has no items left it
+// looks, from its set onward, for the next set that still has some.  Small
+// or finished data sets therefore occupy no work-groups, and the last live
+// sets of an uneven batch get the whole device.  (Counters start at 0 with
+// each band: the iteration set-up and every band decision reset them.)
+constexpr int QCLAIM = 2;
+
+template <int RG>
+__device__ int claim_set(const Dev* __restrict__ devs, int count, int t, int start, int* sh_best) {
+  // every thread checks its share of the sets in rotation order from
+  // `start`; the first with unclaimed items wins
+  if (threadIdx.x == 0) *sh_best = 0x7fffffff;
+  __syncthreads();
+  for (int off = threadIdx.x; off < count; off += blockDim.x) {
+    const int k = (start + off) % count;
+    const Dev& d = devs[k];
+    const int items = band_items<RG>(d, t);
+    if (items > 0 && (int)__atomic_load_n(&d.ctl->q_next, __ATOMIC_RELAXED) < items) {
+      atomicMin(sh_best, off);
+      break;
+    }
+  }
+  __syncthreads();
+  const int best = *sh_best;
+  __syncthreads();
+  return best == 0x7fffffff ? -1 : (start + best) % count;
+}
+
+template <bool MIXED, int RG, int TPW, int PS, typename S>
+__device__ __forceinline__ void k_pair_queue_body(const Dev* __restrict__ devs, int count, int t, BandArgs a) {
+  constexpr int NW = RG * (TB / TPW);
+  __shared__ int s_best, s_i0, s_cnt, s_m, s_tb0, s_ntb;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int lane = threadIdx.x % 64;
+  // reopen every set's score rows for the score launch that follows (the
+  // previous score launch has ended, and the next starts after this one)
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < count; k += blockDim.x) devs[k].ctl->q_rows = 0;
+  int cur = (int)((int64_t)blockIdx.x * count / gridDim.x);
+  int cur_set = -1;
+  unsigned n_eval = 0, n_comp = 0;
+  auto flush = [&](int k) {
+    if (k >= 0 && lane == 0 && n_comp) {
+      const int slot = (int)((blockIdx.x * NW + wave) % PAIR_SLOTS);
+      atomicAdd(&devs[k].pair_slots[slot], (unsigned long long)n_eval);
+      atomicAdd(&devs[k].pair_slots[PAIR_SLOTS + slot], (unsigned long long)n_comp);
+    }
+    n_eval = n_comp = 0;
+  };
+  for (;;) {
+    const int k = claim_set<RG>(devs, count, t, cur, &s_best);
+    if (k < 0) break;
+    if (threadIdx.x == 0) {
+      const Dev& d = devs[k];
+      const int items = band_items<RG>(d, t);
+      const int i0 = (int)atomicAdd(&d.ctl->q_next, (uint32_t)QCLAIM);
+      s_i0 = i0;
+      s_cnt = i0 < items ? min(QCLAIM, items - i0) : 0;
+      s_m = d.ctl->n_alive;
+      s_tb0 = d.ctl->tb_next;
+      s_ntb = d.ctl->ntb_next;
+    }
+    __syncthreads();
+    const int i0 = s_i0, cnt = s_cnt, m = s_m, tb0 = s_tb0, ntb = s_ntb;
+    __syncthreads();
+    cur = k;
+    if (cnt == 0) continue;   // another group took the last items: look again
+    if (k != cur_set) {
+      flush(cur_set);
+      cur_set = k;
+    }
+    for (int item = i0; item < i0 + cnt; ++item)
+      pair_item<MIXED, RG, TPW, PS, S>(devs[k], t, a, item, m, tb0, ntb, n_eval, n_comp);
+  }
+  flush(cur_set);
+}
+
 // BATCH selects the descriptor source at compile time, so each instance
 // holds one copy of the (register-heavy) body.
-template <bool MIXED, int RG, int TPW, int PS, bool BATCH>
+template <bool MIXED, int RG, int TPW, int PS, bool BATCH, typename S>
 __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(const Dev* __restrict__ devs, const Dev one,
                                                                    int t, BandArgs a) {
   if constexpr (BATCH)
-    k_pair_band_body<MIXED, RG, TPW, PS>(devs[blockIdx.z], t, a);
+    k_pair_band_body<MIXED, RG, TPW, PS, S>(devs[blockIdx.z], t, a);
   else
-    k_pair_band_body<MIXED, RG, TPW, PS>(one, t, a);
+    k_pair_band_body<MIXED, RG, TPW, PS, S>(one, t, a);
+}
+
+// The batch form: one persistent grid over the device work queue.
+template <bool MIXED, int RG, int TPW, int PS, typename S>
+__global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_queue(const Dev* __restrict__ devs, int count,
+                                                                    int t, BandArgs a) {
+  k_pair_queue_body<MIXED, RG, TPW, PS, S>(devs, count, t, a);
 }
 
 // Work-group shapes of the pair kernel (results do not depend on them;
@@ -884,14 +1076,14 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(const Dev* _
 // take many generations of groups; later bands are bounded to one.  FP64
 // mode: one row per group, its 8 targets over 4 waves of 2 (its terms need
 // more registers per lane), later bands bounded to two generations.
-template <bool MIXED, int RG, int TPW, int PS>
+template <bool MIXED, int RG, int TPW, int PS, typename S>
 static int resident_groups() {
   static std::atomic<int> cached{0};
   if (cached.load() == 0) {
     int dev = 0, per_cu = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pair_band<MIXED, RG, TPW, PS, false>,
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pair_band<MIXED, RG, TPW, PS, false, S>,
                                                      64 * RG * (TB / TPW), 0) != hipSuccess ||
         per_cu < 1 || cus < 1) {
       per_cu = 1;
@@ -902,12 +1094,12 @@ static int resident_groups() {
   return cached.load();
 }
 
-template <bool MIXED, int RG, int TPW, int PS>
+template <bool MIXED, int RG, int TPW, int PS, typename S>
 static int groups_per_set(const Batch& b, int max_waves) {
-  return std::max(8, max_waves * resident_groups<MIXED, RG, TPW, PS>() / b.count);
+  return std::max(8, max_waves * resident_groups<MIXED, RG, TPW, PS, S>() / b.count);
 }
 
-template <bool MIXED, int RG, int TPW, int PS>
+template <bool MIXED, int RG, int TPW, int PS, typename S>
 static void launch_pair_shape(const Batch& b, int t, const BandArgs& a, int ntb_hint, hipStream_t s,
                               int max_waves, hipEvent_t ev0, hipEvent_t ev1) {
   const int r = b.p_max - t;
@@ -918,40 +1110,48 @@ static void launch_pair_shape(const Batch& b, int t, const BandArgs& a, int ntb_
   // at most max_waves generations of resident work-groups over the batch;
   // sparse bands use one, so no work-group waits for a slot only to find
   // nothing to do
-  const int per_set = groups_per_set<MIXED, RG, TPW, PS>(b, max_waves);
+  const int per_set = groups_per_set<MIXED, RG, TPW, PS, S>(b, max_waves);
   const int G = std::min(ntb * b.nchunk_max * nrg, per_set);  // items when every row is alive
   const int grid = (G + 7) / 8 * 8;
   const dim3 g(grid, 1, b.count), blk(64 * RG * (TB / TPW));
   // the events, when given, take the launch's own start and end times, so
   // they add no packets of their own between the kernels
-  if (b.count == 1)
-    hipExtLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS, false>), g, blk, 0, s, ev0, ev1, 0,
+  if (b.count == 1) {
+    hipExtLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS, false, S>), g, blk, 0, s, ev0, ev1, 0,
                           (const Dev*)nullptr, b.one, t, a);
-  else
-    hipExtLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS, true>), g, blk, 0, s, ev0, ev1, 0,
+  } else if (b.queue) {
+    // the persistent grid: the work-groups the device holds at once
+    const int gq = (resident_groups<MIXED, RG, TPW, PS, S>() + 7) / 8 * 8;
+    hipExtLaunchKernelGGL((k_pair_queue<MIXED, RG, TPW, PS, S>), dim3(gq), blk, 0, s, ev0, ev1, 0,
+                          (const Dev*)b.dd, b.count, t, a);
+  } else {
+    hipExtLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS, true, S>), g, blk, 0, s, ev0, ev1, 0,
                           (const Dev*)b.dd, b.one, t, a);
+  }
 }
 
 void pair_band_shape(const Batch& b, int& rows_per_group, int& groups) {
-  if (b.mixed) {
+  if (b.store32) {
     rows_per_group = 2;
-    groups = groups_per_set<true, 2, 4, 256>(b, 1);
+    groups = groups_per_set<true, 2, 4, 256, float>(b, 1);
+  } else if (b.mixed) {
+    rows_per_group = 2;
+    groups = groups_per_set<true, 2, 4, 256, double>(b, 1);
   } else {
     rows_per_group = 1;
-    groups = groups_per_set<false, 1, 2, 256>(b, 2);
+    groups = groups_per_set<false, 1, 2, 256, double>(b, 2);
   }
 }
 
 hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense, int ntb_hint, hipStream_t s,
                             hipEvent_t ev0, hipEvent_t ev1) {
-  if (b.mixed && dense)
-    launch_pair_shape<true, 2, 4, 256>(b, t, a, ntb_hint, s, 1 << 16, ev0, ev1);
+  const int waves = dense ? 1 << 16 : 1;
+  if (b.store32)
+    launch_pair_shape<true, 2, 4, 256, float>(b, t, a, ntb_hint, s, waves, ev0, ev1);
   else if (b.mixed)
-    launch_pair_shape<true, 2, 4, 256>(b, t, a, ntb_hint, s, 1, ev0, ev1);
-  else if (dense)
-    launch_pair_shape<false, 1, 2, 256>(b, t, a, ntb_hint, s, 1 << 16, ev0, ev1);
+    launch_pair_shape<true, 2, 4, 256, double>(b, t, a, ntb_hint, s, waves, ev0, ev1);
   else
-    launch_pair_shape<false, 1, 2, 256>(b, t, a, ntb_hint, s, 2, ev0, ev1);
+    launch_pair_shape<false, 1, 2, 256, double>(b, t, a, ntb_hint, s, dense ? 1 << 16 : 2, ev0, ev1);
   return hipGetLastError();
 }
 
@@ -1085,58 +1285,64 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
 // (the sum of the bounds of its four entropies) and the bound of the row's
 // score: a test moved by at most eps changes min(0, M)^2 by at most
 // 2 |min(0, M)| eps + 3 eps^2, and not at all when M >= eps.
-__device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
-                                               double gamma_mult) {
+// Batch queue: a set's score rows are closed (no claim can succeed) from its
+// band decision until the next pair launch reopens them.
+constexpr uint32_t Q_CLOSED = 0x40000000u;
+
+// The rows whose tests can have changed in the current band: the variables
+// of the band's target blocks, then the alive variables outside them.  Row
+// index qrow of [0, band_rows) maps to a position, or to -1 (an alive
+// variable that is also a target).
+struct BandRows {
+  int t_lo, t_hi, m, rows;
+};
+
+__device__ __forceinline__ BandRows band_rows(const Dev& d, int t) {
+  const int r = rows_left(d, t);
+  const Ctl* c = d.ctl;
+  BandRows b;
+  b.t_lo = c->tb_next * TB;
+  b.t_hi = min(r, (c->tb_next + c->ntb_next) * TB);
+  b.m = c->n_alive;
+  b.rows = (b.t_hi - b.t_lo) + b.m;
+  return b;
+}
+
+__device__ __forceinline__ int band_row(const Dev& d, const BandRows& br, int qrow) {
+  if (qrow < br.t_hi - br.t_lo) return br.t_lo + qrow;
+  const int y = d.alive_list[qrow - (br.t_hi - br.t_lo)];
+  return (y < br.t_lo || y >= br.t_hi) ? y : -1;
+}
+
+// Row x of the band, by one work-group of 256 threads: the pending tests
+// from the chunk partial sums, then the row's score S_x recomputed over all
+// its tests in ascending original index of the other variable (so its bits
+// do not depend on positions), its rounding bound and its complete flag.
+// In the mixed modes it also forms the rounding bound eps of every new test
+// (the sum of the bounds of its four entropies) and the bound of the row's
+// score: a test moved by at most eps changes min(0, M)^2 by at most
+// 2 |min(0, M)| eps + 3 eps^2, and not at all when M >= eps.
+__device__ __forceinline__ void score_row(const Dev& d, int t, int x) {
   const int r = rows_left(d, t), p = d.p;
-  if (r < 2) return;
-  const int nb = (r + TB - 1) / TB;
   const int buf = t & 1;
   double* __restrict__ M = d.M;
   uint8_t* __restrict__ pend = d.pend;
   const double* __restrict__ P = d.P;
   const double* __restrict__ H = d.H;
-  double* __restrict__ S = d.S;
-  uint8_t* __restrict__ complete = d.complete;
-  const int32_t* alive_list = d.alive_list;
   const int32_t* __restrict__ ord = d.ord[buf];
   const int nchunk = d.nchunk;
   const double n = (double)d.n;
-  const int mixed = d.mixed;
+  const int mixed = d.mixed, store32 = d.store32;
+  const double* __restrict__ dsc = d.dsc[buf];
   double* __restrict__ Meps = d.Meps;
   const double* __restrict__ eH = d.eH;
-  double* __restrict__ eT = d.eT;
-  Ctl* ctl = d.ctl;
-  __shared__ int s_stop, s_m, s_last, s_wrote, s_tb0, s_ntb;
   __shared__ double sh[4];
   __shared__ int shi[4];
-  if (threadIdx.x == 0) {
-    s_stop = halted(ctl) || ctl->done;
-    s_m = ctl->n_alive;
-    s_wrote = 0;
-    s_tb0 = ctl->tb_next;
-    s_ntb = ctl->ntb_next;
-  }
-  __syncthreads();
-  if (s_stop) return;
-  const int tb0 = s_tb0, ntb = s_ntb;
-  const int round_end = tb0 + ntb >= nb ? 1 : 0;  // the last band of the round
-  const int m = s_m;
-  const int t_lo = tb0 * TB, t_hi = min(r, (tb0 + ntb) * TB);
-  const int rows = (t_hi - t_lo) + m;
-  for (int qrow = blockIdx.x; qrow < rows; qrow += gridDim.x) {
-  int x = -1;
-  if (qrow < t_hi - t_lo) {
-    x = t_lo + qrow;
-  } else {
-    const int y = alive_list[qrow - (t_hi - t_lo)];
-    if (y < t_lo || y >= t_hi) x = y;
-  }
-  if (x < 0) continue;  // uniform over the work-group
   double s = 0.0, es = 0.0;
   int incomplete = 0;
   const double hx = H[x];
-  // the row's tests in ascending original index of the other variable, so
-  // the score's bits do not depend on positions
+  const double* sig = d.Sig[buf] + (int64_t)x * p;
+  const double dx = dsc[x];
   for (int q = threadIdx.x; q < r; q += 256) {
     const int w = ord[q];
     if (w == x) continue;
@@ -1157,7 +1363,12 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
       M[o] = mv;
       pend[o] = 0;
       if (mixed) {
-        ev = (eH[x] + eH[w]) + (happ_err_mixed(a0, a1, n) + happ_err_mixed(a2, a3, n));
+        double din = 0.0;
+        if (store32) {
+          const double b = sig[w] * (dx * dsc[w]);   // as the pair kernel forms it
+          din = 3.0 / sqrt(1.0 - b * b);
+        }
+        ev = (eH[x] + eH[w]) + (happ_err_mixed(a0, a1, n, din) + happ_err_mixed(a2, a3, n, din));
         Meps[o] = ev;
       }
     } else if (__builtin_isnan(mv)) {
@@ -1175,25 +1386,30 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
   if (mixed) es = block_sum256(es, sh);
   incomplete = block_or256(incomplete, shi);
   if (threadIdx.x == 0) {
-    S[x] = s;
-    eT[x] = es;
-    complete[x] = incomplete ? 0 : 1;
-    s_wrote = 1;
+    d.S[x] = s;
+    d.eT[x] = es;
+    d.complete[x] = incomplete ? 0 : 1;
   }
-  }
-  // The last work-group to finish takes the iteration-level decision.  Each
-  // group publishes its scores (release) before it counts itself in; the
-  // last one acquires them.  Nothing waits, so no group can be held up.
-  __syncthreads();
+}
+
+// The iteration-level decision after a band of data set d (one work-group
+// of 256 threads, once every row of the band is scored): termination,
+// threshold update, root, threshold state and the next band's target
+// blocks; then the band counters are cleared for the next launch.
+__device__ __forceinline__ void band_decision(const Dev& d, int t, const BandArgs& a, double gamma_mult) {
+  const int r = rows_left(d, t);
+  const int nb = (r + TB - 1) / TB;
+  const int buf = t & 1;
+  Ctl* ctl = d.ctl;
+  __shared__ int s_tb0, s_ntb;
   if (threadIdx.x == 0) {
-    if (s_wrote) __threadfence();
-    const unsigned prev = atomicAdd(&ctl->arrivals, 1u);
-    s_last = prev == gridDim.x - 1 ? 1 : 0;
+    s_tb0 = ctl->tb_next;
+    s_ntb = ctl->ntb_next;
   }
   __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  decide_group(S, d.alive, complete, d.alive_list, r, round_end, t, gamma_mult, d.forced, d.forced_len,
+  const int tb0 = s_tb0, ntb = s_ntb;
+  const int round_end = tb0 + ntb >= nb ? 1 : 0;  // the last band of the round
+  decide_group(d.S, d.alive, d.complete, d.alive_list, r, round_end, t, gamma_mult, d.forced, d.forced_len,
                d.idx[buf], ctl);
   if (threadIdx.x == 0 && !ctl->done && ctl->status == ST_OK) {
     // the next band: after the end of a round every block at once; within
@@ -1207,11 +1423,11 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
       int k = d.band_k0;
       if (d.band_adapt) {
         const int m_next = max(ctl->n_alive, 1);
-        const double want = a.band_target / ((double)TB * (double)m_next * n);
+        const double want = a.band_target / ((double)TB * (double)m_next * (double)d.n);
         // whole rounds of the work-groups: a target block brings one item
         // per row group and chunk, and a band whose items overrun a round
         // by a few leaves most groups idle for a second one
-        const int per_block = (m_next + a.rows_per_group - 1) / a.rows_per_group * nchunk;
+        const int per_block = (m_next + a.rows_per_group - 1) / a.rows_per_group * d.nchunk;
         const int fill = a.groups / per_block;  // blocks that fill one round
         if (fill >= 1)
           k = fill * max(1, (int)ceil(want / (double)fill));
@@ -1223,7 +1439,114 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a,
       ctl->ntb_next = min(k, left);
     }
   }
-  if (threadIdx.x == 0) ctl->arrivals = 0;  // ready for the next launch
+  if (threadIdx.x == 0) {
+    // ready for the next band: its pair launch starts claiming items at 0
+    // (no pair launch is running now); the score rows of this band stay
+    // closed for the rest of this launch and the next pair launch reopens
+    // them (batch queue)
+    ctl->arrivals = 0;
+    ctl->q_next = 0;
+    ctl->q_rows = Q_CLOSED;
+  }
+}
+
+// One data set (grid z, or alone): the work-groups walk the band's rows;
+// the last work-group to finish takes the decision.  Each group publishes
+// its scores (release) before it counts itself in; the last one acquires
+// them.  Nothing waits, so no group can be held up.
+__device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a, double gamma_mult) {
+  const int r = rows_left(d, t);
+  if (r < 2) return;
+  Ctl* ctl = d.ctl;
+  __shared__ int s_stop, s_last, s_wrote;
+  __shared__ BandRows s_br;
+  if (threadIdx.x == 0) {
+    s_stop = halted(ctl) || ctl->done;
+    s_wrote = 0;
+    s_br = band_rows(d, t);
+  }
+  __syncthreads();
+  if (s_stop) return;
+  const BandRows br = s_br;
+  for (int qrow = blockIdx.x; qrow < br.rows; qrow += gridDim.x) {
+    const int x = band_row(d, br, qrow);
+    if (x < 0) continue;  // uniform over the work-group
+    score_row(d, t, x);
+    if (threadIdx.x == 0) s_wrote = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_wrote) __threadfence();
+    const unsigned prev = atomicAdd(&ctl->arrivals, 1u);
+    s_last = prev == gridDim.x - 1 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  band_decision(d, t, a, gamma_mult);
+}
+
+// A batch on the device work queue: work-groups claim rows of any data set
+// (Ctl::q_rows) and count each finished row in (Ctl::arrivals, released
+// after the row's scores); the group that finishes a set's last row takes
+// that set's decision.
+template <int RG>
+__device__ int claim_score_set(const Dev* __restrict__ devs, int count, int t, int start, int* sh_best) {
+  if (threadIdx.x == 0) *sh_best = 0x7fffffff;
+  __syncthreads();
+  for (int off = threadIdx.x; off < count; off += blockDim.x) {
+    const int k = (start + off) % count;
+    const Dev& d = devs[k];
+    const Ctl* c = d.ctl;
+    if (rows_left(d, t) < 2 || halted(c) || c->done) continue;
+    const int rows = (min(rows_left(d, t), (c->tb_next + c->ntb_next) * TB) - c->tb_next * TB) + c->n_alive;
+    if ((int)__atomic_load_n(&c->q_rows, __ATOMIC_RELAXED) < rows) {
+      atomicMin(sh_best, off);
+      break;
+    }
+  }
+  __syncthreads();
+  const int best = *sh_best;
+  __syncthreads();
+  return best == 0x7fffffff ? -1 : (start + best) % count;
+}
+
+__device__ __forceinline__ void k_score_queue_body(const Dev* __restrict__ devs, int count, int t, BandArgs a,
+                                                   double gamma_mult) {
+  __shared__ int s_best, s_q, s_last;
+  __shared__ BandRows s_br;
+  int cur = (int)((int64_t)blockIdx.x * count / gridDim.x);
+  for (;;) {
+    const int k = claim_score_set<1>(devs, count, t, cur, &s_best);
+    if (k < 0) break;
+    cur = k;
+    const Dev& d = devs[k];
+    if (threadIdx.x == 0) {
+      // a claim below the row count holds the set's band open (its decision
+      // waits for this row), so its band fields read after it are stable
+      s_q = (int)atomicAdd(&d.ctl->q_rows, 1u);
+      s_br = band_rows(d, t);
+    }
+    __syncthreads();
+    const BandRows br = s_br;
+    const int qrow = s_q;
+    __syncthreads();
+    if (qrow >= br.rows) continue;
+    const int x = band_row(d, br, qrow);
+    if (x >= 0) score_row(d, t, x);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      const unsigned prev = atomicAdd(&d.ctl->arrivals, 1u);
+      s_last = prev == (unsigned)br.rows - 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      band_decision(d, t, a, gamma_mult);
+      __syncthreads();
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_score(const Dev* __restrict__ devs, const Dev one, int t, BandArgs a,
@@ -1234,6 +1557,11 @@ __global__ __launch_bounds__(256) void k_score(const Dev* __restrict__ devs, con
     k_score_body(one, t, a, gamma_mult);
 }
 
+__global__ __launch_bounds__(256) void k_score_queue(const Dev* __restrict__ devs, int count, int t, BandArgs a,
+                                                     double gamma_mult) {
+  k_score_queue_body(devs, count, t, a, gamma_mult);
+}
+
 hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_mult, int dense, int ntb_hint,
                         hipStream_t s) {
   const int r = b.p_max - t;
@@ -1241,6 +1569,20 @@ hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_m
   const int nb = (r + TB - 1) / TB;
   // rows when every variable is alive; after the first band of an iteration
   // few are, and a smaller grid keeps idle groups from filling the launch
+  if (b.count > 1 && b.queue) {
+    // rows of every set on the device work queue, about 4 work-groups per CU
+    static int cus = 0;
+    if (cus == 0) {
+      int dev = 0;
+      if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                                                    dev) != hipSuccess || cus < 1)
+        cus = 256;
+    }
+    const int rows_all = (std::min(r, std::max(1, std::min(ntb_hint, nb)) * TB) + r) * b.count;
+    hipLaunchKernelGGL(k_score_queue, dim3(std::max(8, std::min(4 * cus, rows_all))), dim3(256), 0, s,
+                       (const Dev*)b.dd, b.count, t, a, gamma_mult);
+    return hipGetLastError();
+  }
   const int rows = std::min(r, std::max(1, std::min(ntb_hint, nb)) * TB) + r;
   const int cap = std::max(8, (dense ? 512 : 256) / std::min(b.count, 16));
   hipLaunchKernelGGL(k_score, dim3(std::min(rows, cap), 1, b.count), dim3(256), 0, s, DEVS(b), t, a, gamma_mult);
@@ -1412,7 +1754,7 @@ __global__ __launch_bounds__(256) void k_rank(const Dev* __restrict__ devs, cons
 // iteration) it also sums the new row's entropy terms over its samples, in
 // the mode's precision (binary32 lane sums of at most 32 terms in the mixed
 // mode), for the next iteration's entropy.
-template <bool MIXED>
+template <bool MIXED, typename S>
 __device__ __forceinline__ void k_update_rows_body(const Dev& d, int t, int want_h) {
   const int r = rows_left(d, t), p = d.p;
   const Ctl* ctl = d.ctl;
@@ -1420,8 +1762,8 @@ __device__ __forceinline__ void k_update_rows_body(const Dev& d, int t, int want
   const int segs = entropy_segments_of(n);
   if (r < 2 || (int)blockIdx.y >= r - 1 || (int)blockIdx.x >= segs || halted(ctl) || !ctl->done) return;
   const int buf = t & 1;
-  const double* __restrict__ Z = d.Z[buf];
-  double* __restrict__ Zn = d.Z[buf ^ 1];
+  const S* __restrict__ Z = static_cast<const S*>(d.Z[buf]);
+  S* __restrict__ Zn = static_cast<S*>(d.Z[buf ^ 1]);
   const double* __restrict__ Sig = d.Sig[buf];
   const double* __restrict__ dsc = d.dsc[buf];
   const int root = ctl->root;
@@ -1429,15 +1771,23 @@ __device__ __forceinline__ void k_update_rows_body(const Dev& d, int t, int want
   const int w = d.perm[wn];                   // old position
   const double dw = dsc[w], dr = dsc[root];
   const double b = Sig[(int64_t)w * p + root] * dw * dr;   // correlation of the normalised rows
-  const double sc = 1.0 / sqrt(1.0 - b * b);
-  const double* zr = Z + (int64_t)root * ldz;
-  const double* zw = Z + (int64_t)w * ldz;
-  double* zo = Zn + (int64_t)wn * ldz;
+  const double om = 1.0 - b * b;
+  // every pair passed 1 - b^2 > 1e-12 at the iteration's start; this guard
+  // only keeps a rounding difference from dividing by zero
+  if (!(om > 0.0)) {
+    if (threadIdx.x == 0) raise_error(const_cast<Ctl*>(ctl), ST_DEGENERATE, d.idx[buf][w], d.idx[buf][root]);
+    return;
+  }
+  const double sc = 1.0 / sqrt(om);
+  const S* zr = Z + (int64_t)root * ldz;
+  const S* zw = Z + (int64_t)w * ldz;
+  S* zo = Zn + (int64_t)wn * ldz;
   const int64_t step = (int64_t)segs * 256;
+  // binary64 arithmetic in every mode; binary32 rows are rounded once, on the store
   if (!want_h) {
 #pragma unroll 4
     for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += step)
-      zo[k] = (zw[k] - b * zr[k]) * sc;   // the rows are stored normalised
+      zo[k] = (S)(((double)zw[k] - b * (double)zr[k]) * sc);   // the rows are stored normalised
     return;
   }
   double lc = 0.0, g = 0.0;
@@ -1447,17 +1797,17 @@ __device__ __forceinline__ void k_update_rows_body(const Dev& d, int t, int want
     while (k < n) {
       float flc = 0.f, fg = 0.f;
       for (int c = 0; c < 32 && k < n; ++c, k += step) {
-        const double zk = (zw[k] - b * zr[k]) * sc;
-        zo[k] = zk;
-        terms_mixed((float)zk, ca, cg, flc, fg);
+        const double zk = ((double)zw[k] - b * (double)zr[k]) * sc;
+        zo[k] = (S)zk;
+        terms_mixed((float)zk, ca, cg, flc, fg);   // the value the row holds
       }
       lc += (double)flc * LN2;
       g += (double)fg;
     }
   } else {
     for (; k < n; k += step) {
-      const double zk = (zw[k] - b * zr[k]) * sc;
-      zo[k] = zk;
+      const double zk = ((double)zw[k] - b * (double)zr[k]) * sc;
+      zo[k] = (S)zk;
       terms_f64(zk, lc, g);
     }
   }
@@ -1471,13 +1821,13 @@ __device__ __forceinline__ void k_update_rows_body(const Dev& d, int t, int want
   }
 }
 
-template <bool MIXED>
+template <bool MIXED, typename S>
 __global__ __launch_bounds__(256) void k_update_rows(const Dev* __restrict__ devs, const Dev one, int t,
                                                      int want_h) {
   if (devs)
-    k_update_rows_body<MIXED>(devs[blockIdx.z], t, want_h);
+    k_update_rows_body<MIXED, S>(devs[blockIdx.z], t, want_h);
   else
-    k_update_rows_body<MIXED>(one, t, want_h);
+    k_update_rows_body<MIXED, S>(one, t, want_h);
 }
 
 // Work-group 0 first records the iteration's results (or halts an iteration
@@ -1516,7 +1866,9 @@ __device__ __forceinline__ void k_update_sigma_body(const Dev& d, int t, int rec
       const double da = dsc[a], db = dsc[b], dr = dsc[root];
       const double ba = Sig[(int64_t)a * p + root] * da * dr, bb = Sig[(int64_t)b * p + root] * db * dr;
       const double bab = Sig[(int64_t)a * p + b] * (da * db);   // symmetric in a and b
-      val = (bab - ba * bb) / (sqrt(1.0 - ba * ba) * sqrt(1.0 - bb * bb));
+      // both factors are positive: every pair passed 1 - b^2 > 1e-12 at the
+      // iteration's start (the row update guards the root's pairs)
+      val = (bab - ba * bb) / (sqrt(fmax(1.0 - ba * ba, DEGEN_EPS)) * sqrt(fmax(1.0 - bb * bb, DEGEN_EPS)));
     }
     Sn[(int64_t)an * p + bn] = val;
   }
@@ -1537,10 +1889,13 @@ hipError_t launch_iter_end(const Batch& b, int t, int refresh, hipStream_t s) {
   if (e != hipSuccess) return e;
   const int xblocks = entropy_segments_of(b.n_max);
   const int want_h = refresh ? 0 : 1;
-  if (b.mixed)
-    hipLaunchKernelGGL(k_update_rows<true>, dim3(xblocks, rn, b.count), dim3(256), 0, s, DEVS(b), t, want_h);
+  const dim3 ug(xblocks, rn, b.count);
+  if (b.store32)
+    hipLaunchKernelGGL((k_update_rows<true, float>), ug, dim3(256), 0, s, DEVS(b), t, want_h);
+  else if (b.mixed)
+    hipLaunchKernelGGL((k_update_rows<true, double>), ug, dim3(256), 0, s, DEVS(b), t, want_h);
   else
-    hipLaunchKernelGGL(k_update_rows<false>, dim3(xblocks, rn, b.count), dim3(256), 0, s, DEVS(b), t, want_h);
+    hipLaunchKernelGGL((k_update_rows<false, double>), ug, dim3(256), 0, s, DEVS(b), t, want_h);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t total = std::max<int64_t>((int64_t)rn * rn, rn);
@@ -1587,6 +1942,9 @@ __device__ __forceinline__ void k_resume_body(const Dev& d) {
   if (ctl->status == ST_OK) {
     ctl->halt = 0;
     ctl->halt_iter = -1;
+    ctl->arrivals = 0;
+    ctl->q_next = 0;
+    ctl->q_rows = 0;
   }
 }
 
@@ -1599,6 +1957,111 @@ __global__ void k_resume(const Dev* __restrict__ devs, const Dev one) {
 
 hipError_t launch_resume(const Batch& b, hipStream_t s) {
   hipLaunchKernelGGL(k_resume, dim3(1, 1, b.count), dim3(1), 0, s, DEVS(b));
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Alg. 1, last step: causal strengths B from the causal order K
+// ============================================================================
+// Each variable is regressed on every variable before it in K (Sec. 2.3,
+// covariance-based least squares along the order).  All regressions come
+// from one factorisation: with C the correlation matrix of the input permuted
+// into K order and C = L L^T its Cholesky factor, L_unit = L diag(L)^-1 is
+// the unit lower triangle of C = L_unit D L_unit^T, and row t of
+// I - L_unit^-1 holds the least-squares coefficients of variable K[t] on
+// K[0..t) (standardised units; the sample covariances fit exactly, so this is
+// the least-squares solution of the data).  They are then rescaled to the
+// input's units, b_ij = b~_ij sd_i / sd_j.
+
+// C0 = the correlation matrix of the normalised input rows, from the first
+// Gram (G_ij d_i d_j, unit diagonal).
+__global__ void k_corr_snapshot(const Dev d) {
+  const int p = d.p;
+  const double* __restrict__ G = d.Sig[0];
+  const double* __restrict__ dsc = d.dsc[0];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)p * p;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / p), j = (int)(e % p);
+    d.C0[e] = i == j ? 1.0 : G[e] * (dsc[i] * dsc[j]);
+  }
+}
+
+hipError_t launch_corr_snapshot(const Dev& d, hipStream_t s) {
+  const int64_t pp = (int64_t)d.p * d.p;
+  hipLaunchKernelGGL(k_corr_snapshot, dim3((unsigned)std::min<int64_t>(1024, (pp + 255) / 256)), dim3(256), 0, s,
+                     d);
+  return hipGetLastError();
+}
+
+// Column j of the Cholesky factor (left-looking): one wave per row i >= j
+// forms sum_{k<j} L_ik L_jk and, redundantly and identically in every wave,
+// the pivot C_jj - sum_{k<j} L_jk^2.  A pivot that is not positive (the
+// variables before K[j] determine it) is reported as degenerate.
+__global__ __launch_bounds__(256) void k_chol_col(const Dev d, int j) {
+  const int p = d.p;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int i = j + blockIdx.x * 4 + wave;
+  if (i >= p || halted(d.ctl)) return;
+  const int32_t* __restrict__ K = d.order;
+  const double* __restrict__ C = d.C0;
+  double* __restrict__ L = d.Lch;
+  const double* Lj = L + (int64_t)j * p;
+  const double* Li = L + (int64_t)i * p;
+  double sjj = 0.0, sij = 0.0;
+  for (int k = lane; k < j; k += 64) {
+    const double ljk = Lj[k];
+    sjj += ljk * ljk;
+    sij += Li[k] * ljk;
+  }
+  sjj = wave_sum(sjj);
+  sij = wave_sum(sij);
+  const double piv = C[(int64_t)K[j] * p + K[j]] - sjj;
+  if (!(piv > DEGEN_EPS)) {
+    if (i == j && lane == 0) raise_error(d.ctl, ST_DEGENERATE, K[j], -1);
+    return;
+  }
+  const double ljj = sqrt(piv);
+  if (lane == 0) L[(int64_t)i * p + j] = i == j ? ljj : (C[(int64_t)K[i] * p + K[j]] - sij) / ljj;
+}
+
+// Column j of B_K = I - L_unit^-1 by forward substitution, one work-group:
+// m_j = 1 and m_i = -sum_{k=j}^{i-1} (L_ik / L_kk) m_k, written in the
+// input's indices and units as B[K[i]][K[j]] = -m_i sd_K[i] / sd_K[j]
+// (w_k = m_k / L_kk is kept in LDS).
+__global__ __launch_bounds__(256) void k_unit_inverse_col(const Dev d) {
+  const int p = d.p, j = blockIdx.x;
+  if (j >= p || halted(d.ctl)) return;
+  extern __shared__ double w[];
+  __shared__ double sh[4];
+  const int32_t* __restrict__ K = d.order;
+  const double* __restrict__ L = d.Lch;
+  double* __restrict__ B = d.Bout;
+  if (threadIdx.x == 0) w[0] = 1.0 / L[(int64_t)j * p + j];
+  __syncthreads();
+  const double sd_j = sqrt(d.stats[2 * K[j] + 1]);
+  for (int i = j + 1; i < p; ++i) {
+    const double* Li = L + (int64_t)i * p;
+    double s = 0.0;
+    for (int k = j + threadIdx.x; k < i; k += 256) s += Li[k] * w[k - j];
+    s = block_sum256(s, sh);
+    if (threadIdx.x == 0) {
+      w[i - j] = -s / Li[i];
+      B[(int64_t)K[i] * p + K[j]] = s * sqrt(d.stats[2 * K[i] + 1]) / sd_j;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_estimate_B(const Dev& d, hipStream_t s) {
+  const int p = d.p;
+  hipError_t e = launch_fill(d.Bout, (int64_t)p * p, 0.0, s);
+  if (e != hipSuccess) return e;
+  for (int j = 0; j < p; ++j) {
+    hipLaunchKernelGGL(k_chol_col, dim3((p - j + 3) / 4), dim3(256), 0, s, d, j);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_unit_inverse_col, dim3(p), dim3(256), sizeof(double) * p, s, d);
   return hipGetLastError();
 }
 

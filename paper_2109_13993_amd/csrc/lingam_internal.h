@@ -5,7 +5,26 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "lingam.h"
+
 namespace lingam {
+
+// A fixed block of device memory on the current device that a call carves
+// all of its buffers from (no allocation); `who` names the owner in error
+// messages.
+struct FixedBlock {
+  char* base;
+  uint64_t cap;
+  const char* who;
+};
+// lingam_fit_order with every device buffer carved from `block` and nothing
+// allocated: no device memory, streams or events are created, and the search
+// runs on opts->stream (NULL = the null stream).  opts->workspace and
+// opts->profile are rejected.  (driver.cpp)
+lingam_status fit_order_in_block(const void* X, int64_t n, int64_t p, const lingam_opts* opts,
+                                 lingam_result* out, const FixedBlock& block);
+// Detail text for lingam_last_error() on the calling thread.  (driver.cpp)
+void set_last_error(const char* msg);
 
 // Variables per target block of the pair kernel.
 constexpr int TB = 8;
@@ -38,7 +57,10 @@ struct Ctl {
   int32_t status;       // Status of the first error
   int32_t bad_i, bad_j; // compacted positions (pair error) or original index (row error)
   int32_t round;        // threshold round of the current iteration
-  uint32_t arrivals;     // work-groups of the running score launch that have finished
+  uint32_t arrivals;     // work-groups (one data set) or rows (batch queue) of the running score
+                         // launch that have finished
+  uint32_t q_next;       // batch queue: pair-kernel items of the band claimed so far
+  uint32_t q_rows;       // batch queue: score rows of the band claimed so far
   int32_t n_alive;        // entries of the alive list (variables with S <= gamma)
   int32_t tb_next;        // target blocks [tb_next, tb_next + ntb_next) of the next band
   int32_t ntb_next;
@@ -66,8 +88,11 @@ struct Dev {
   unsigned long long* pair_slots = nullptr;
   int band_k0 = 4;           // target blocks of an iteration's first band (every block: no threshold)
   int band_adapt = 1;        // 1 = size later bands from the alive count, 0 = band_k0 blocks each
-  int64_t ldz = 0;           // row stride of Z (doubles), multiple of 64
-  double* Z[2] = {nullptr, nullptr};      // p x ldz normalised rows (ping-pong by iteration parity)
+  int64_t ldz = 0;           // row stride of Z (elements), multiple of SUB
+  // p x ldz normalised rows (ping-pong by iteration parity), binary64, or
+  // binary32 when store32 is set (FP32-storage precision)
+  void* Z[2] = {nullptr, nullptr};
+  int store32 = 0;
   // Sig holds G, the covariance of the rows the Gram was taken of (ld = p),
   // and dsc the row scales d_i = 1/sqrt(G_ii): the normalised rows are d_i z_i
   // and their correlation is b_ij = G_ij d_i d_j.  The entropy pass at the
@@ -114,7 +139,14 @@ struct Dev {
   double* stats = nullptr;   // [2*p] per-row mean/variance of the input (diagnostics)
   double* Gp = nullptr;      // [gram_slices_max][p][p] per-slice partial Gram
   int gram_slices_max = 1;   // largest sample split of the Gram
+  // causal strengths from the order (Alg. 1, last step), when asked for
+  double* C0 = nullptr;      // p x p correlation of the normalised input
+  double* Lch = nullptr;     // p x p Cholesky factor of C0 in the order's permutation (lower)
+  double* Bout = nullptr;    // p x p B in the input's indices and units
 };
+
+// Largest p for which B is estimated (one column of the inverse in LDS).
+constexpr int B_MAX_P = 8000;
 
 // Samples per pair-kernel band that later bands of round 0 aim at: their
 // target-block count is chosen so that (alive rows) x (targets) x n is
@@ -150,6 +182,8 @@ struct Batch {
   int nchunk_max = 1;
   int gram_slices_max = 1;
   int mixed = 0;
+  int store32 = 0;           // rows stored in binary32 (every data set of the batch)
+  int queue = 1;             // batches: pair and score work on the device work queue
 };
 
 // ---- launch wrappers (kernels.hip) --------------------------------------
@@ -183,6 +217,10 @@ hipError_t launch_resume(const Batch& b, hipStream_t s);
 hipError_t launch_gather(const double* X, int64_t n_src, int64_t p, const int64_t* idx, int64_t n_idx,
                          double* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
+// C0 from the first Gram (after launch_gram at t = 0).
+hipError_t launch_corr_snapshot(const Dev& d, hipStream_t s);
+// B from C0 and the causal order in d.order (host-side descriptor d).
+hipError_t launch_estimate_B(const Dev& d, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t count, uint8_t v, hipStream_t s);
 
 }  // namespace lingam

@@ -20,7 +20,7 @@ HEADER = os.path.join(ROOT, "include", "lingam.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lingam_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lingam_[A-Za-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -168,3 +168,42 @@ def test_batch_validation(lib):
     o.forced_order = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     o.forced_len = 2
     assert _batch_call(lib, [(X, None)], o) == lg.E_UNSUPPORTED
+
+
+def test_workspace_size_is_consistent(lib):
+    # the size comes from the same layout code as the call itself: a batch of
+    # one data set needs exactly what the single call needs, and the size
+    # grows with the options that add buffers
+    X = np.zeros((30, 5000))
+    o = lg.default_opts()
+    single = lib.lingam_workspace_size(5000, 30, ctypes.byref(o))
+    sets = (lg.LingamDataset * 1)()
+    sets[0].X = ctypes.c_void_p(X.ctypes.data)
+    sets[0].p, sets[0].n = X.shape
+    assert lib.lingam_workspace_size_batch(1, sets, ctypes.byref(o)) == single
+    o.x_on_device = 1
+    dev = lib.lingam_workspace_size(5000, 30, ctypes.byref(o))
+    assert dev < single and single - dev >= 30 * 5000 * 8
+    o.record_M_iters = 3
+    assert lib.lingam_workspace_size(5000, 30, ctypes.byref(o)) >= dev + 3 * 30 * 30 * 8
+    assert lib.lingam_workspace_size_batch(0, sets, ctypes.byref(o)) == 0
+
+
+def test_too_small_workspace_rejected_before_device_work(lib):
+    # the workspace is checked on the host: a pointer that is never
+    # dereferenced (no device work is issued) gives NOMEM or INVALID
+    X = np.zeros((4, 300))
+    need = lib.lingam_workspace_size(300, 4, None)
+    o = lg.default_opts()
+    o.workspace = ctypes.c_void_p(1 << 40)
+    o.workspace_bytes = need - 1
+    st, msg = _call(X, 300, 4, o)
+    assert st == lg.E_NOMEM and str(need) in msg
+    o.workspace = ctypes.c_void_p((1 << 40) + 64)     # not 256-byte aligned
+    o.workspace_bytes = need
+    st, msg = _call(X, 300, 4, o)
+    assert st == lg.E_INVALID and "aligned" in msg
+    o = lg.default_opts()
+    o.workspace = ctypes.c_void_p(1 << 40)
+    o.workspace_bytes = 16
+    assert _batch_call(lib, [(np.zeros((3, 10)), None)], o) == lg.E_NOMEM

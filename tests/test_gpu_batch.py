@@ -50,14 +50,16 @@ def _single(item, **kw):
     return lg.fit_order(item, **kw)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32_storage"])
 def test_batch_equals_single_runs(precision):
+    # on the device work queue (default) and with one grid slice per set
     sets = _mixed_batch(3)
-    res = lg.fit_order_batch(sets, precision=precision)
-    assert len(res) == len(sets)
-    for k, item in enumerate(sets):
-        _same(res[k], _single(item, precision=precision), "%s set %d" % (precision, k))
-    _log("%s batch of %d: %.1f ms" % (precision, len(sets), res[0].seconds_total * 1e3))
+    for queue in (True, False):
+        res = lg.fit_order_batch(sets, precision=precision, queue=queue)
+        assert len(res) == len(sets)
+        for k, item in enumerate(sets):
+            _same(res[k], _single(item, precision=precision), "%s queue=%s set %d" % (precision, queue, k))
+        _log("%s batch of %d (queue %s): %.1f ms" % (precision, len(sets), queue, res[0].seconds_total * 1e3))
 
 
 def test_batch_stragglers_and_options():
@@ -100,3 +102,24 @@ def test_bootstrap_batch_config4_shape():
     ps = sum(r.pair_samples for r in res)
     _log("bootstrap 32 x (100 x 5000): %.1f ms, %.3e pair-samples/s" % (
         res[0].seconds_total * 1e3, ps / res[0].seconds_total))
+
+
+def test_batch_graph_windows_replay():
+    # windows of 16 iterations captured into HIP graphs on the first call and
+    # replayed by later calls on the same workspace, with other device work
+    # and synchronisations in between: every replay gives the eager results
+    import torch
+    sets = _mixed_batch(11)
+    eager = lg.fit_order_batch(sets, precision="mixed")
+    need = lg.batch_workspace_size(sets, precision="mixed")
+    ws = torch.empty(need + 4096, dtype=torch.uint8, device="cuda:0")
+    x = torch.randn(1 << 20, device="cuda:0")
+    for rep in range(4):
+        res = lg.fit_order_batch(sets, precision="mixed", workspace=ws, graph=True)
+        for k in range(len(sets)):
+            _same(res[k], eager[k], "graph replay %d set %d" % (rep, k))
+        # eager work of the program between replays
+        lg.fit_order(sets[1], precision="mixed")
+        x.mul_(1.0001).add_(0.5)
+        torch.cuda.synchronize()
+        _log("graph replay %d: %.1f ms" % (rep, res[0].seconds_total * 1e3))

@@ -144,6 +144,24 @@ def test_config2_fp64_parity(cfg2):
     assert small.pairs_evaluated < g.pairs_evaluated
 
 
+def test_config2_mixed_free_running_order(cfg2):
+    # the mixed-precision search run free (not teacher-forced) must find the
+    # oracle's order; the gap rule must hold wherever it certifies
+    ds, o = cfg2
+    g = lg.fit_order(ds.X, precision="mixed")
+    p = ds.X.shape[0]
+    diff = np.flatnonzero(g.order != o["order"])
+    cert = 0
+    for t in range(p - 1):
+        top, ok = _gap_certified(g.T, g.T_err, g.T_state, t)
+        cert += ok
+        if ok:
+            assert o["order"][t] == top, "iteration %d certified but the oracle's root differs" % t
+    _log("mixed cfg2 free running: order differs at %s; %d of %d iterations certified" % (
+        diff[:5].tolist(), cert, p - 1))
+    assert diff.size == 0
+
+
 @pytest.mark.parametrize("every", [4, 0])
 def test_refresh_period_fp64(cfg2, every):
     # Gram refresh every 4 iterations, or only the rank-1 UpdateCovMat
@@ -314,6 +332,36 @@ def test_mixed_teacher_forced_scores():
     _log("mixed cfg2: %d of %d iterations certified by the gap rule" % (certified, ds.X.shape[0] - 1))
 
 
+def test_fp32_storage_scores_and_order(cfg2):
+    # binary32 rows: iteration 0 holds the rows as first rounded, so every
+    # score must lie within its stated bound of the oracle's; the search
+    # run free must find the oracle's order, and the gap rule must hold
+    ds, o = cfg2
+    p = ds.X.shape[0]
+    g = lg.fit_order(ds.X, precision="fp32_storage", use_threshold=False, record_M_iters=1)
+    fin = np.isfinite(o["T"][0])
+    dT = np.abs(g.T[0][fin] - o["T"][0][fin])
+    tol = 1e-9 * np.abs(o["T"][0][fin]) + 1e-12
+    ratio = dT / (g.T_err[0][fin] + tol)
+    dM = np.nanmax(np.abs(g.M[0] - o["M"][0]))
+    _log("fp32 storage cfg2 t=0: max|dM| %.3e max|dT| %.3e, max |dT|/(bound+tol) %.3e" % (
+        dM, dT.max(), ratio.max()))
+    assert ratio.max() <= 1.0
+    f = lg.fit_order(ds.X, precision="fp32_storage")
+    cert = 0
+    for t in range(p - 1):
+        top, ok = _gap_certified(f.T, f.T_err, f.T_state, t)
+        cert += ok
+        if ok:
+            assert o["order"][t] == top, "iteration %d certified but the oracle's root differs" % t
+    diff = np.flatnonzero(f.order != o["order"])
+    _log("fp32 storage cfg2 free running: order differs at %s; %d of %d certified" % (
+        diff[:5].tolist(), cert, p - 1))
+    assert diff.size == 0
+    # half the row storage of the binary64 modes
+    assert lg.workspace_size(10000, 100, "fp32_storage") < lg.workspace_size(10000, 100, "mixed")
+
+
 def _gap_certified(T, E, state, t):
     """Root position of iteration t of a mixed run and whether the rounding
     bounds separate it from every other variable (a pruned variable's partial
@@ -357,6 +405,58 @@ def test_mixed_free_running_order_gap_rule(cfg3, chunk):
 
 
 # ---- edge cases and input forms ------------------------------------------------
+
+def _hadamard_rows(p):
+    # p <= 3 mutually orthogonal zero-mean rows of +-1 over n = 4 samples:
+    # every covariance is exactly 0 (all partial sums of +-c^2 are exact),
+    # every row has the same |values| and its u exp(-u^2/2) terms cancel
+    # exactly, so every test is exactly 0 and every score ties at 0
+    return np.array([[1.0, 1.0, -1.0, -1.0], [1.0, -1.0, 1.0, -1.0], [1.0, -1.0, -1.0, 1.0]])[:p]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_ties_go_to_the_lowest_original_index(precision):
+    import itertools
+    for p in (2, 3):
+        H = _hadamard_rows(p)
+        for perm in itertools.permutations(range(p)):
+            X = H[list(perm)]
+            g = lg.fit_order(X, precision=precision, record_M_iters=1)
+            off = ~np.eye(p, dtype=bool)
+            assert np.all(g.M[0][off] == 0.0), (precision, perm, g.M[0])   # an exact tie
+            assert list(g.order) == list(range(p)), (precision, perm, g.order)
+            assert list(oracle.fit_order(X)["order"]) == list(range(p))
+
+
+def test_degenerate_pair_found_when_pruned():
+    # a nearly collinear pair (1 - corr^2 < 1e-12) among 64 variables, with the
+    # threshold on and one target block per band: the pair is checked at the
+    # start of the iteration whether or not the threshold would prune it
+    ds = synth.lingam_dataset(64, 4000, 0.1, "laplace", rng=np.random.default_rng(31))
+    X = ds.X.copy()
+    X[63] = 2.0 * X[40] + 1e-7 * np.random.default_rng(32).standard_normal(4000) * X[40].std()
+    with pytest.raises(oracle.OracleError) as eo:
+        oracle.fit_order(X)
+    assert eo.value.status == oracle.E_DEGENERATE
+    for kw in (dict(precision="fp64", band_blocks=1), dict(precision="mixed")):
+        with pytest.raises(lg.LingamError) as e:
+            lg.fit_order(X, **kw)
+        assert e.value.status == lg.E_DEGENERATE and {e.value.bad_i, e.value.bad_j} == {40, 63}, kw
+
+
+def test_caller_workspace_gives_the_same_result():
+    import torch
+    ds = synth.lingam_dataset(40, 6000, 0.2, "mixed", rng=np.random.default_rng(33))
+    need = lg.workspace_size(6000, 40, precision="mixed")
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+    a = lg.fit_order(ds.X, precision="mixed")
+    b = lg.fit_order(ds.X, precision="mixed", workspace=ws)
+    assert np.array_equal(a.order, b.order)
+    assert np.array_equal(a.T, b.T, equal_nan=True) and np.array_equal(a.T_err, b.T_err, equal_nan=True)
+    small = torch.empty(need - 256, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(lg.LingamError) as e:
+        lg.fit_order(ds.X, precision="mixed", workspace=small)
+    assert e.value.status == lg.E_NOMEM
 
 def test_one_and_two_variables():
     rng = np.random.default_rng(3)

@@ -119,6 +119,32 @@ def test_uncorrelated_pair_gives_exact_zero():
     assert oracle.compare(a, b) == 0.0
 
 
+def _hadamard_rows(p):
+    # p <= 3 mutually orthogonal zero-mean rows of +-1 over n = 4 samples:
+    # every covariance is exactly 0, every row has the same |values|, and
+    # each row's u exp(-u^2/2) terms cancel exactly, so all tests are 0
+    return np.array([[1.0, 1.0, -1.0, -1.0], [1.0, -1.0, 1.0, -1.0], [1.0, -1.0, -1.0, 1.0]])[:p]
+
+
+def test_ties_go_to_the_lowest_original_index():
+    # the reading taken for ties (the paper is silent): U keeps the original
+    # order, so among equal minimum scores the lowest original index wins.
+    # Exact ties: tests that are exactly 0 give every score exactly 0.
+    a = np.tile([1.0, -1.0, 1.0, -1.0], 250) * np.repeat(np.arange(1, 251, dtype=float), 4)
+    b = np.tile([1.0, 1.0, -1.0, -1.0], 250) * np.repeat(np.arange(1, 251, dtype=float), 4)
+    for X in (np.stack([a, b]), np.stack([b, a])):
+        res = oracle.fit_order(X, M_iters=1)
+        assert res["M"][0][0, 1] == 0.0 and res["T"][0][0] == res["T"][0][1] == 0.0
+        assert list(res["order"]) == [0, 1]
+    import itertools
+    H = _hadamard_rows(3)
+    for perm in itertools.permutations(range(3)):
+        res = oracle.fit_order(H[list(perm)], M_iters=1)
+        off = ~np.eye(3, dtype=bool)
+        assert np.all(res["M"][0][off] == 0.0)
+        assert list(res["order"]) == [0, 1, 2]
+
+
 def test_antisymmetry_is_bitwise():
     ds = synth.lingam_dataset(6, 2000, 0.5, "laplace", rng=np.random.default_rng(3))
     M = oracle.fit_order(ds.X, M_iters=1)["M"][0]
@@ -203,6 +229,17 @@ def test_forced_prefix_and_max_roots():
     part = oracle.fit_order(ds.X, max_roots=3)
     assert list(part["order"][:3]) == list(free["order"][:3]) and list(part["order"][3:]) == [-1] * 4
     assert np.all(np.isnan(part["T"][3:]))
+
+
+def test_pair_once_gives_the_ordered_evaluation_bitwise():
+    # evaluating each unordered pair once and negating it for the reverse
+    # test (messaging, Sec. 3.1) changes no output bit
+    for p, n, seed in ((9, 1500, 4), (23, 3000, 5)):
+        ds = synth.lingam_dataset(p, n, 0.3, "mixed", rng=np.random.default_rng(seed))
+        a = oracle.fit_order(ds.X, M_iters=p)
+        b = oracle.fit_order(ds.X, M_iters=p, pair_once=True)
+        for k in ("order", "T", "H", "M", "B"):
+            assert np.array_equal(a[k], b[k], equal_nan=True), k
 
 
 def test_result_independent_of_thread_count():
@@ -292,3 +329,50 @@ def test_matches_numpy_mini_reference(seed, p):
     fin = np.isfinite(T)
     assert np.array_equal(fin, np.isfinite(res["T"]))
     np.testing.assert_allclose(res["T"][fin], T[fin], rtol=1e-9, atol=1e-13)
+
+
+# ---- Alg. 1, last step: causal strengths from the order ------------------------
+
+def test_estimate_B_recovers_worked_example():
+    # the SEM of Sec. 2.1-2.2 (Eq. (base_mat_ex)): with the true order, least
+    # squares recovers b15 = 3, b23 = 6, b24 = -3, b41 = 4, b53 = 5 and zeros
+    # elsewhere to O(1/sqrt(n)); with the oracle's own order too
+    g = _golden("paper_example.json")
+    B = np.array(g["B_rows_1based"], dtype=float)
+    rng = np.random.default_rng(2021)
+    n = 100000
+    N = rng.uniform(-math.sqrt(3), math.sqrt(3), (5, n))
+    X = np.linalg.solve(np.eye(5) - B, N)
+    true_order = [k - 1 for k in g["causal_order_1based"]]
+    for order in (true_order, oracle.fit_order(X)["order"]):
+        Bh = oracle.estimate_B(X, order)
+        assert np.max(np.abs(Bh - B)) < 20.0 / math.sqrt(n), Bh
+    assert oracle.estimate_B(X, true_order)[0, 4] == pytest.approx(3.0, abs=0.05)
+
+
+def test_estimate_B_exact_with_orthogonal_noise():
+    # noise rows made exactly zero-mean and mutually orthogonal over the
+    # sample: least squares then returns B itself (no sampling error), so
+    # the only difference is rounding
+    rng = np.random.default_rng(8)
+    p, n = 7, 400
+    E = rng.laplace(size=(p, n))
+    E -= E.mean(axis=1, keepdims=True)
+    Q, _ = np.linalg.qr(E.T)                   # orthonormal columns, all orthogonal to 1
+    Q -= Q.mean(axis=0)                        # (already ~0: E was centred)
+    E = Q.T * np.arange(1, p + 1)[:, None]
+    B = np.tril(rng.uniform(0.5, 2.0, (p, p)) * rng.choice([-1.0, 1.0], (p, p)) * (rng.random((p, p)) < 0.6), -1)
+    X = np.linalg.solve(np.eye(p) - B, E)
+    X += rng.uniform(-5.0, 5.0, (p, 1))        # offsets: the intercept must absorb them
+    perm = rng.permutation(p)
+    Xp, Bp = X[perm], B[np.ix_(perm, perm)]
+    inv = np.empty(p, dtype=int)
+    inv[perm] = np.arange(p)
+    order = list(inv)                          # generation order in output indices
+    Bh = oracle.estimate_B(Xp, order)
+    assert np.max(np.abs(Bh - Bp)) < 1e-10
+    # nothing is assigned to a variable that does not precede
+    pos = np.empty(p, dtype=int)
+    pos[order] = np.arange(p)
+    later = pos[None, :] >= pos[:, None]
+    assert np.all(Bh[later] == 0.0)
