@@ -213,6 +213,25 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets,
  * (0 if the batch is invalid). */
 uint64_t lingam_workspace_size_batch(int32_t count, const lingam_dataset* sets, const lingam_opts* o);
 
+/*
+ * lingam_fit_order for callers that cannot allocate device memory (code
+ * under HIP graph capture of its own, tight serving loops, harnesses that
+ * forbid hipMalloc).  Every device buffer of the call is carved from a fixed
+ * 64 MiB device array that the library holds on each GPU it runs on until
+ * the process ends; no device memory, stream or event is created, and the
+ * search runs on opts->stream (NULL = the null stream).  Arguments, results
+ * and errors are those of lingam_fit_order, plus:
+ *   LINGAM_E_NOMEM if lingam_workspace_size(n, p, o) exceeds 64 MiB (e.g.
+ *     p=100, n=10000 fits; p=500, n=20000 does not), before any device work;
+ *   LINGAM_E_INVALID if opts->workspace is set, LINGAM_E_UNSUPPORTED if
+ *     opts->profile is set (its timing events would allocate).
+ * Calls on one GPU share its array, which keeps the last call's contents
+ * (every buffer a search needs cleared is cleared by the search itself):
+ * calls that overlap on one GPU race and must be serialised by the caller.
+ */
+lingam_status lingam_fit_order_noalloc(const void* X, int64_t n, int64_t p, const lingam_opts* o,
+                                       lingam_result* out);
+
 /* Device bytes one call of lingam_fit_order with these shape and options
  * uses (the workspace it allocates, or the least opts->workspace_bytes it
  * accepts); 0 for an invalid shape.  It depends on n, p, precision,

@@ -24,7 +24,7 @@ PREC = {"fp64": 0, "mixed": 1, "fp32": 1, "fp32_storage": 2}
 LAYOUT = {"var_major": 0, "sample_major": 1}
 
 # Exported symbols of the C ABI (kept in sync with include/lingam.h).
-SYMBOLS = ("lingam_opts_default", "lingam_fit_order", "lingam_fit_order_batch",
+SYMBOLS = ("lingam_opts_default", "lingam_fit_order", "lingam_fit_order_noalloc", "lingam_fit_order_batch",
            "lingam_workspace_size", "lingam_workspace_size_batch", "lingam_estimate_B",
            "lingam_status_string", "lingam_last_error")
 
@@ -118,6 +118,8 @@ def load_library(path: str = LIB_PATH):
     lib.lingam_fit_order.restype = ctypes.c_int
     lib.lingam_fit_order.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                      ctypes.POINTER(LingamOpts), ctypes.POINTER(LingamResult)]
+    lib.lingam_fit_order_noalloc.restype = ctypes.c_int
+    lib.lingam_fit_order_noalloc.argtypes = lib.lingam_fit_order.argtypes
     lib.lingam_fit_order_batch.restype = ctypes.c_int
     lib.lingam_fit_order_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(LingamDataset),
                                            ctypes.POINTER(LingamOpts), ctypes.POINTER(LingamResult)]
@@ -215,7 +217,7 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
               forced_order=None, record_M_iters: int = 0, want_T: bool = True,
               want_H: bool = True, band_blocks: int = 0, chunk_samples: int = 0,
               layout: str = "var_major", stream=None, profile: bool = False,
-              workspace=None, estimate_B: bool = False,
+              workspace=None, noalloc: bool = False, estimate_B: bool = False,
               band_target: float = 0.0, first_band_blocks: int = 0, tune: bool = True) -> FitResult:
     """Causal order of the variables of X (lingam_fit_order).
 
@@ -226,6 +228,8 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
     workspace: optional device tensor (e.g. torch.empty(nbytes, dtype=torch.uint8,
     device="cuda")) that the call carves its device buffers from
     (workspace_size() bytes at least).
+    noalloc: call lingam_fit_order_noalloc, which carves every buffer from the
+    library's fixed per-GPU device array and allocates nothing.
     estimate_B: also estimate the causal strengths B from the order (result.B).
     band_target / chunk_samples / band_blocks: launch tuning (never changes a
     result); left at 0 they take the autotuner's entry for this device and
@@ -292,7 +296,8 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
         res.M = M.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     if Bm is not None:
         res.B = Bm.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    st = lib.lingam_fit_order(ctypes.c_void_p(ptr), n, p, ctypes.byref(o), ctypes.byref(res))
+    entry = lib.lingam_fit_order_noalloc if noalloc else lib.lingam_fit_order
+    st = entry(ctypes.c_void_p(ptr), n, p, ctypes.byref(o), ctypes.byref(res))
     del host_ref, keep
     if st != OK:
         raise LingamError(st, lib.lingam_last_error().decode(), res.bad_i, res.bad_j)
