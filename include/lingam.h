@@ -129,6 +129,10 @@ typedef struct lingam_opts {
   int32_t first_band_blocks;   /* tuning: target blocks of an iteration's first threshold band, the
                                   later bands sized as by default (band_blocks = 0); 0 (default) = 4
                                   for a single MIXED / FP32_STORAGE search, 1 otherwise */
+  int32_t messaging;           /* 1 (default) = each unordered pair evaluated once, the reverse test
+                                  its exact negation (Sec. 3.1 messaging); 0 = every variable
+                                  evaluates its own tests, each pair once per direction (the
+                                  ablation without messaging: the same results, twice the pairs) */
 } lingam_opts;
 
 /* Outputs.  All arrays are host memory owned by the caller; NULL = not wanted. */
@@ -150,6 +154,11 @@ typedef struct lingam_result {
                            x_i, the least-squares coefficient of x_j when x_i is regressed
                            (with an intercept) on every variable before it in the order; 0
                            where x_j does not precede x_i */
+  double* T_err_prob;   /* [p*p], mixed modes: a probable bound on |T - T_exact| beside the
+                           worst-case T_err_bound: the rounding errors taken as independent
+                           and zero-mean (Hoeffding, failure probability 2.5e-14 per entropy
+                           estimate) plus the hardware exp2/log2 systematic error; 0 in FP64
+                           mode, NaN where T is NaN */
   uint64_t pairs_evaluated;   /* unordered pairs whose test was needed and evaluated */
   uint64_t pair_samples;      /* pairs_evaluated x n (the throughput unit) */
   uint64_t pairs_computed;    /* pairs actually run by the kernel (>= pairs_evaluated) */
@@ -255,6 +264,35 @@ uint64_t lingam_workspace_size(int64_t n, int64_t p, const lingam_opts* o);
  * variable is a linear function of those before it. */
 lingam_status lingam_estimate_B(const void* X, int64_t n, int64_t p, const int32_t* order,
                                 const lingam_opts* o, double* B);
+
+/* Measured error of the hardware binary32 exp2 and log2 (v_exp_f32,
+ * v_log_f32) that the MIXED and FP32_STORAGE per-sample terms use, over every
+ * binary32 argument of the ranges they take: exp2 on [-126, 0] (relative
+ * error; below -126 the term is under 2^-126 absolutely) and log2 on [1, 2]
+ * (absolute error), against the binary64 library functions.  Units of
+ * u32 = 2^-24.  The rounding bound T_err_bound assumes exp2 within
+ * LINGAM_EXP2_ERR and log2 within LINGAM_LOG2_ERR; lingam_check_terms lets a
+ * caller (and the tests) confirm that on the device at hand. */
+#define LINGAM_EXP2_ERR 2.0
+#define LINGAM_LOG2_ERR 1.5
+/* ... and the probable bound T_err_prob assumes their systematic error (the
+ * largest mean error within one binade of the argument) within these.  On
+ * MI355X the sweep measures exp2 within 1.42 (largest binade mean 0.52) and
+ * log2 within 1.00 (mean -0.19). */
+#define LINGAM_EXP2_BIAS 0.75
+#define LINGAM_LOG2_BIAS 0.3
+typedef struct lingam_term_check {
+  double exp2_max_rel;          /* largest |exp2~(x) - 2^x| / 2^x */
+  double exp2_mean_rel;         /* mean signed relative error over all arguments */
+  double exp2_max_binade_mean;  /* largest |mean signed error| within one binade of |x| */
+  double log2_max_abs;          /* largest |log2~(x) - log2 x| */
+  double log2_mean_abs;         /* mean signed error */
+  uint64_t exp2_count, log2_count;  /* arguments evaluated */
+} lingam_term_check;
+
+/* Run the sweep on `device` (-1 = the current one); about 1.1e9 + 8.4e6
+ * evaluations. */
+lingam_status lingam_check_terms(int32_t device, lingam_term_check* out);
 
 /* Static text for a status code. */
 const char* lingam_status_string(lingam_status s);

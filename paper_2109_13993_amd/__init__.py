@@ -25,7 +25,7 @@ LAYOUT = {"var_major": 0, "sample_major": 1}
 
 # Exported symbols of the C ABI (kept in sync with include/lingam.h).
 SYMBOLS = ("lingam_opts_default", "lingam_fit_order", "lingam_fit_order_noalloc", "lingam_fit_order_batch",
-           "lingam_workspace_size", "lingam_workspace_size_batch", "lingam_estimate_B",
+           "lingam_workspace_size", "lingam_workspace_size_batch", "lingam_estimate_B", "lingam_check_terms",
            "lingam_status_string", "lingam_last_error")
 
 
@@ -56,6 +56,7 @@ class LingamOpts(ctypes.Structure):
         ("graph", ctypes.c_int32),
         ("band_target", ctypes.c_double),
         ("first_band_blocks", ctypes.c_int32),
+        ("messaging", ctypes.c_int32),
     ]
 
 
@@ -68,6 +69,7 @@ class LingamResult(ctypes.Structure):
         ("M", ctypes.POINTER(ctypes.c_double)),
         ("T_err_bound", ctypes.POINTER(ctypes.c_double)),
         ("B", ctypes.POINTER(ctypes.c_double)),
+        ("T_err_prob", ctypes.POINTER(ctypes.c_double)),
         ("pairs_evaluated", ctypes.c_uint64),
         ("pair_samples", ctypes.c_uint64),
         ("pairs_computed", ctypes.c_uint64),
@@ -91,6 +93,18 @@ class LingamDataset(ctypes.Structure):
         ("p", ctypes.c_int64),
         ("sample_idx", ctypes.POINTER(ctypes.c_int64)),
         ("n_idx", ctypes.c_int64),
+    ]
+
+
+class LingamTermCheck(ctypes.Structure):
+    _fields_ = [
+        ("exp2_max_rel", ctypes.c_double),
+        ("exp2_mean_rel", ctypes.c_double),
+        ("exp2_max_binade_mean", ctypes.c_double),
+        ("log2_max_abs", ctypes.c_double),
+        ("log2_mean_abs", ctypes.c_double),
+        ("exp2_count", ctypes.c_uint64),
+        ("log2_count", ctypes.c_uint64),
     ]
 
 
@@ -132,6 +146,8 @@ def load_library(path: str = LIB_PATH):
     lib.lingam_estimate_B.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(LingamOpts),
                                       ctypes.POINTER(ctypes.c_double)]
+    lib.lingam_check_terms.restype = ctypes.c_int
+    lib.lingam_check_terms.argtypes = [ctypes.c_int32, ctypes.POINTER(LingamTermCheck)]
     lib.lingam_status_string.restype = ctypes.c_char_p
     lib.lingam_status_string.argtypes = [ctypes.c_int]
     lib.lingam_last_error.restype = ctypes.c_char_p
@@ -149,6 +165,7 @@ class FitResult:
     M: Optional[np.ndarray] = None    # [k, p, p] test matrices of the first k iterations
     T_err: Optional[np.ndarray] = None  # [p, p] rounding bound of T (mixed; 0 in FP64 mode)
     B: Optional[np.ndarray] = None    # [p, p] causal strengths (estimate_B), B[i, j] = effect of x_j on x_i
+    T_err_prob: Optional[np.ndarray] = None  # [p, p] probable rounding bound of T (mixed modes)
     pairs_evaluated: int = 0
     pair_samples: int = 0
     pairs_computed: int = 0
@@ -218,7 +235,8 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
               want_H: bool = True, band_blocks: int = 0, chunk_samples: int = 0,
               layout: str = "var_major", stream=None, profile: bool = False,
               workspace=None, noalloc: bool = False, estimate_B: bool = False,
-              band_target: float = 0.0, first_band_blocks: int = 0, tune: bool = True) -> FitResult:
+              band_target: float = 0.0, first_band_blocks: int = 0, tune: bool = True,
+              messaging: bool = True) -> FitResult:
     """Causal order of the variables of X (lingam_fit_order).
 
     X is a p x n array (row i = samples of variable i; layout="sample_major"
@@ -274,6 +292,7 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
     p, n = (shape[0], shape[1]) if layout == "var_major" else (shape[1], shape[0])
     o.band_target = float(band_target)
     o.first_band_blocks = int(first_band_blocks)
+    o.messaging = 1 if messaging else 0
     if tune:
         _apply_tuned(o, "single", precision, p, n)
     order = np.full(p, -1, dtype=np.int32)
@@ -281,6 +300,7 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
     Ts = np.zeros((p, p), dtype=np.uint8) if want_T else None
     H = np.full((p, p), np.nan) if want_H else None
     Terr = np.full((p, p), np.nan) if want_T else None
+    Terrp = np.full((p, p), np.nan) if want_T else None
     M = np.full((record_M_iters, p, p), np.nan) if record_M_iters > 0 else None
     Bm = np.full((p, p), np.nan) if estimate_B else None
     res = LingamResult()
@@ -292,6 +312,7 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
         res.H = H.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     if Terr is not None:
         res.T_err_bound = Terr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        res.T_err_prob = Terrp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     if M is not None:
         res.M = M.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     if Bm is not None:
@@ -301,7 +322,7 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
     del host_ref, keep
     if st != OK:
         raise LingamError(st, lib.lingam_last_error().decode(), res.bad_i, res.bad_j)
-    return FitResult(order=order, T=T, T_state=Ts, H=H, M=M, T_err=Terr, B=Bm,
+    return FitResult(order=order, T=T, T_state=Ts, H=H, M=M, T_err=Terr, B=Bm, T_err_prob=Terrp,
                      pairs_evaluated=res.pairs_evaluated, pair_samples=res.pair_samples,
                      pairs_computed=res.pairs_computed, threshold_rounds=res.threshold_rounds,
                      bands=res.bands, seconds_total=res.seconds_total,
@@ -373,12 +394,14 @@ def fit_order_batch(datasets, precision: str = "fp64", use_threshold: bool = Tru
                  T=np.full((p, p), np.nan) if want_T else None,
                  T_state=np.zeros((p, p), dtype=np.uint8) if want_T else None,
                  H=np.full((p, p), np.nan) if want_H else None,
-                 T_err=np.full((p, p), np.nan) if want_T else None)
+                 T_err=np.full((p, p), np.nan) if want_T else None,
+                 T_err_prob=np.full((p, p), np.nan) if want_T else None)
         outs[k].order = r["order"].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         if want_T:
             outs[k].T = r["T"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             outs[k].T_state = r["T_state"].ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
             outs[k].T_err_bound = r["T_err"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            outs[k].T_err_prob = r["T_err_prob"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         if want_H:
             outs[k].H = r["H"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         results.append(r)
@@ -391,6 +414,7 @@ def fit_order_batch(datasets, precision: str = "fp64", use_threshold: bool = Tru
     for k, r in enumerate(results):
         out = outs[k]
         res.append(FitResult(order=r["order"], T=r["T"], T_state=r["T_state"], H=r["H"], T_err=r["T_err"],
+                             T_err_prob=r["T_err_prob"],
                              pairs_evaluated=out.pairs_evaluated, pair_samples=out.pair_samples,
                              pairs_computed=out.pairs_computed, threshold_rounds=out.threshold_rounds,
                              bands=out.bands, seconds_total=out.seconds_total,
@@ -434,14 +458,25 @@ def estimate_B(X, order, precision: str = "fp64", layout: str = "var_major", str
     return B
 
 
+def check_terms(device: int = -1) -> dict:
+    """Measured error of the hardware binary32 exp2 / log2 over the argument
+    ranges of the per-sample terms, in units of 2^-24 (lingam_check_terms)."""
+    lib = load_library()
+    r = LingamTermCheck()
+    st = lib.lingam_check_terms(int(device), ctypes.byref(r))
+    if st != OK:
+        raise LingamError(st, lib.lingam_last_error().decode())
+    return {f: getattr(r, f) for f, _ in LingamTermCheck._fields_}
+
+
 def status_string(status: int) -> str:
     return load_library().lingam_status_string(int(status)).decode()
 
 
-def batch_workspace_size(datasets, precision: str = "fp64") -> int:
+def batch_workspace_size(datasets, precision: str = "fp64", chunk_samples: int = 0) -> int:
     """Device bytes of one fit_order_batch call over `datasets` (host inputs,
     as fit_order_batch takes them): lingam_workspace_size_batch."""
-    o, _ = _make_opts(precision)
+    o, _ = _make_opts(precision, chunk_samples=chunk_samples)
     count = len(datasets)
     sets = (LingamDataset * count)()
     keep = []

@@ -189,7 +189,9 @@ def tune_batch(sets, precision: str = "mixed", reps: int = 3, log=print, path: s
     p, n = batch_shape(sets)
     space = {k: (v[precision] if isinstance(v, dict) else v) for k, v in BATCH_SPACE.items()}
     start = {"chunk_samples": 2048, "first_band_blocks": 1, "band_target": 2e7, "batch_queue": 1, "graph": 0}
-    ws = torch.empty(lg.batch_workspace_size(sets, precision) + 4096, dtype=torch.uint8, device="cuda:0")
+    # one workspace for every trial: the largest layout is the shortest chunk's
+    need = max(lg.batch_workspace_size(sets, precision, chunk_samples=c) for c in space["chunk_samples"])
+    ws = torch.empty(need + 4096, dtype=torch.uint8, device="cuda:0")
 
     def timer(params):
         kw = dict(params)

@@ -166,6 +166,7 @@ lingam_status validate_opts(const lingam_opts& o) {
     return fail(LINGAM_E_INVALID, "chunk_samples must be a multiple of 256");
   if (o.band_blocks < 0) return fail(LINGAM_E_INVALID, "band_blocks < 0");
   if (o.first_band_blocks < 0) return fail(LINGAM_E_INVALID, "first_band_blocks < 0");
+  if (o.messaging != 0 && o.messaging != 1) return fail(LINGAM_E_INVALID, "messaging must be 0 or 1");
   if (o.record_M_iters < 0) return fail(LINGAM_E_INVALID, "record_M_iters < 0");
   if (o.estimate_B != 0 && o.estimate_B != 1) return fail(LINGAM_E_INVALID, "estimate_B must be 0 or 1");
   if (o.batch_queue != 0 && o.batch_queue != 1) return fail(LINGAM_E_INVALID, "batch_queue must be 0 or 1");
@@ -218,6 +219,7 @@ void reset_result(lingam_result* out, int64_t p, int rec) {
   if (out->M) for (int64_t k = 0; k < (int64_t)rec * p * p; ++k) out->M[k] = NAN;
   if (out->T_err_bound) for (int64_t k = 0; k < p * p; ++k) out->T_err_bound[k] = NAN;
   if (out->B) for (int64_t k = 0; k < p * p; ++k) out->B[k] = NAN;
+  if (out->T_err_prob) for (int64_t k = 0; k < p * p; ++k) out->T_err_prob[k] = NAN;
   out->pairs_evaluated = out->pair_samples = out->pairs_computed = 0;
   out->threshold_rounds = out->bands = 0;
   out->seconds_total = out->seconds_device = out->seconds_pair_kernel = 0.0;
@@ -293,6 +295,10 @@ Dev carve_set(Arena& al, int64_t n, int64_t p, const Plan& pl, const lingam_opts
   d.eT = al.get<double>(P);
   d.Meps = al.get<double>(pp);
   d.Terr = al.get<double>(pp);
+  d.eHp = al.get<double>(P);
+  d.Mepsp = al.get<double>(pp);
+  d.eTp = al.get<double>(P);
+  d.Terrp = al.get<double>(pp);
   d.M = al.get<double>(pp);
   d.S = al.get<double>(P);
   d.alive = al.get<uint8_t>(P);
@@ -320,6 +326,7 @@ Dev carve_set(Arena& al, int64_t n, int64_t p, const Plan& pl, const lingam_opts
     d.Bout = al.get<double>(pp);
   }
   d.band_k0 = pl.band_blocks;
+  d.messaging = o.messaging ? 1 : 0;
   d.band_adapt = o.band_blocks > 0 ? 0 : 1;
   return d;
 }
@@ -342,6 +349,7 @@ void init_set(const Dev& d, const lingam_opts& o, int limit, hipStream_t s, std:
   HIPCHK(launch_fill_u8(d.Tstate, (int64_t)pp, 0, s));
   HIPCHK(launch_fill(d.Hall, (int64_t)pp, NAN, s));
   HIPCHK(launch_fill(d.Terr, (int64_t)pp, NAN, s));
+  HIPCHK(launch_fill(d.Terrp, (int64_t)pp, NAN, s));
   if (d.Mrec) HIPCHK(launch_fill(d.Mrec, (int64_t)d.rec * (int64_t)pp, NAN, s));
   HIPCHK(launch_fill_u8(reinterpret_cast<uint8_t*>(d.order), (int64_t)(4 * P), 0xff, s));
   HIPCHK(launch_fill_u8(reinterpret_cast<uint8_t*>(d.pair_slots), (int64_t)(2 * PAIR_SLOTS * 8), 0, s));
@@ -479,6 +487,8 @@ void copy_results(const Dev& d, const Ctl& c, int64_t n, lingam_result* out, hip
   if (out->H) HIPCHK(hipMemcpyAsync(out->H, d.Hall, sizeof(double) * pp, hipMemcpyDeviceToHost, s));
   if (out->T_err_bound)
     HIPCHK(hipMemcpyAsync(out->T_err_bound, d.Terr, sizeof(double) * pp, hipMemcpyDeviceToHost, s));
+  if (out->T_err_prob)
+    HIPCHK(hipMemcpyAsync(out->T_err_prob, d.Terrp, sizeof(double) * pp, hipMemcpyDeviceToHost, s));
   if (out->M && d.rec > 0)
     HIPCHK(hipMemcpyAsync(out->M, d.Mrec, sizeof(double) * pp * d.rec, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -552,6 +562,7 @@ struct BatchLayout {
   std::vector<char> base_upload;    // per set: 1 if this set's base is uploaded here
   std::vector<int64_t*> idx;        // per bootstrap set: device sample indices
   Dev* dd = nullptr;
+  int32_t* act = nullptr;           // the sets in order of the iteration they end at (work queue)
 };
 
 BatchLayout layout_batch(Arena& ar, int32_t count, const lingam_dataset* sets, const Plan& pl,
@@ -597,6 +608,7 @@ BatchLayout layout_batch(Arena& ar, int32_t count, const lingam_dataset* sets, c
     L.devs[(size_t)k] = d;
   }
   L.dd = ar.get<Dev>((size_t)count);
+  L.act = ar.get<int32_t>((size_t)count);
   return L;
 }
 
@@ -819,7 +831,7 @@ uint64_t batch_layout_key(const char* base, uint64_t bytes, int32_t count, const
   const uint64_t fields[] = {(uint64_t)o.precision, (uint64_t)o.use_threshold, (uint64_t)o.max_roots,
                              (uint64_t)o.batch_queue, (uint64_t)refresh_every, (uint64_t)pl.chunk,
                              (uint64_t)pl.band_blocks, (uint64_t)o.band_blocks, (uint64_t)o.first_band_blocks,
-                             (uint64_t)o.x_dtype,
+                             (uint64_t)o.x_dtype, (uint64_t)o.messaging,
                              (uint64_t)o.layout, (uint64_t)o.x_on_device};
   for (uint64_t v : fields) h = mix64(h, v);
   uint64_t g0, gm, bt;
@@ -936,6 +948,7 @@ void lingam_opts_default(lingam_opts* o) {
   o->stream = nullptr;
   o->profile = 0;
   o->batch_queue = 1;
+  o->messaging = 1;
 }
 
 const char* lingam_status_string(lingam_status s) {
@@ -1004,6 +1017,44 @@ lingam_status lingam_estimate_B(const void* X, int64_t n, int64_t p, const int32
   res.order = ord.data();
   res.B = B;
   return fit_single(X, n, p, o, &res, nullptr, order);
+}
+
+lingam_status lingam_check_terms(int32_t device, lingam_term_check* out) {
+  g_last_error.clear();
+  if (!out) return fail(LINGAM_E_INVALID, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  OwnedMem own;
+  OwnedStream os;
+  DeviceGuard dg;
+  try {
+    dg.set(device);
+    HIPCHK(hipMalloc(&own.p, sizeof(TermSweep)));
+    HIPCHK(hipStreamCreate(&os.s));
+    os.owned = true;
+    HIPCHK(launch_fill_u8(static_cast<uint8_t*>(own.p), sizeof(TermSweep), 0, os.s));
+    HIPCHK(launch_term_sweep(static_cast<TermSweep*>(own.p), os.s));
+    TermSweep r;
+    HIPCHK(hipMemcpyAsync(&r, own.p, sizeof(TermSweep), hipMemcpyDeviceToHost, os.s));
+    HIPCHK(hipStreamSynchronize(os.s));
+    double mx[2];
+    std::memcpy(mx, r.max_bits, sizeof(mx));
+    const uint64_t exp_count = 0x42FC0000ull + 1, log_count = 0x40000000ull - 0x3F800000ull + 1;
+    out->exp2_max_rel = mx[0];
+    out->exp2_mean_rel = r.sum[0] / (double)exp_count;
+    out->log2_max_abs = mx[1];
+    out->log2_mean_abs = r.sum[1] / (double)log_count;
+    out->exp2_count = exp_count;
+    out->log2_count = log_count;
+    // binades of |x|: exponent fields 0 (zero and subnormals) .. 132 hold 2^23
+    // arguments each, field 133 ([64, 126]) the rest
+    for (int e = 0; e <= 133; ++e) {
+      const double cnt = e < 133 ? 8388608.0 : (double)(0x42FC0000ull - 0x42800000ull + 1);
+      out->exp2_max_binade_mean = std::max(out->exp2_max_binade_mean, std::fabs(r.binade_sum[0][e] / cnt));
+    }
+  } catch (const HipFail& e) {
+    return status_from(e);
+  }
+  return LINGAM_OK;
 }
 
 lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, const lingam_opts* opts,
@@ -1097,6 +1148,18 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
     HIPCHK(hipMemcpyAsync(ctls, c0.data(), sizeof(Ctl) * count, hipMemcpyHostToDevice, f.s));
     HIPCHK(hipStreamSynchronize(f.s));
 
+    // the work queue's list of sets, latest-ending first: the sets with an
+    // iteration at t are a prefix of it
+    std::vector<int32_t> act_order((size_t)count);
+    std::vector<int> act_until((size_t)count);
+    for (int k = 0; k < count; ++k) act_order[(size_t)k] = k;
+    auto until = [&](int k) { return std::min(f.limits[(size_t)k], (int)f.ps[(size_t)k] - 1); };
+    std::stable_sort(act_order.begin(), act_order.end(), [&](int x, int y) { return until(x) > until(y); });
+    for (int k = 0; k < count; ++k) act_until[(size_t)k] = until(act_order[(size_t)k]);
+    HIPCHK(hipMemcpyAsync(L.act, act_order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, f.s));
+    HIPCHK(hipStreamSynchronize(f.s));
+    f.b.act = L.act;
+    f.b.act_until = act_until.data();
     f.b.dd = dd;
     f.b.count = count;
     f.b.p_max = (int)p_max;

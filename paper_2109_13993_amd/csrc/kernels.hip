@@ -124,36 +124,71 @@ __device__ __forceinline__ void terms_mixed(float x, float ca, float cg, float& 
   g = __builtin_fmaf(x, e2, g);
 }
 
-// A-priori rounding bound of one entropy estimate of the mixed mode, from
-// its sums s_lc = sum (log cosh u + ln 2) and s_g = sum u exp(-u^2/2) over n
-// samples of a unit-variance u (so mean |u| <= 1).  With u32 = 2^-24 and the
-// hardware exp2 / log2 taken within 4 u32 relative / 8 u32 absolute:
-//   per term of log cosh: residual and scale rounding (3 u32 on the exp2
-//   argument, slope <= 1/2) 4.33 u32 |u|, exp2 + add + log2 12.33 u32, the
-//   fma u32 |t|; binary32 lane sums of <= 32 terms add 31 u32 sum |t|, so in
-//   natural units  dE1 <= u32 (32 s_lc / n + ln 2 (4.33 + 12.33));
-//   per term of u exp(-u^2/2): 5 u32 |g| + 2.5 u32 |u|^3 exp(-u^2/2) <= 5.93 u32,
-//   lane sums 32 u32 sum |g| with |g| <= exp(-1/2):  dE2 <= 25.4 u32.
+// Rounding bounds of one entropy estimate of the mixed modes, from its sums
+// s_lc = sum (log cosh u + ln 2) and s_g = sum u exp(-u^2/2) over n samples
+// of a unit-variance u (so mean |u| <= 1 and mean u^2 = 1).  u32 = 2^-24;
+// the hardware exp2 and log2 are within E = LINGAM_EXP2_ERR u32 (relative)
+// and L = LINGAM_LOG2_ERR u32 (absolute) on the arguments used, which
+// lingam_check_terms measures.  Per term t of log cosh (natural units):
+// the argument of exp2 carries 3 u32 (residual, scale and product
+// roundings), which the final fma halves: 3.0 u32 |u|; exp2, the add and
+// log2: (2.10 + E + ln 2 L) u32; the fma u32 |t|.  Per term of
+// g = u exp(-u^2/2): 5 u32 on the exp2 argument gives 2.5 u32 |u|^3 e^-u^2/2
+// <= 2.9 u32, exp2 and the operand (1 + E) u32 |g|, the fma u32 |g|, with
+// |g| <= e^-1/2.  Lane sums of at most 32 terms in binary32.
+//
+// Worst case (happ_err_mixed): every error at its bound, lane sums at
+// 31 u32 sum |t|:
+//   dE1 <= u32 (32 s_lc / n + 3.0 + 2.10 + E + ln 2 L),
+//   dE2 <= u32 (32 e^-1/2 + (1 + E) e^-1/2 + 2.9).
+// Probable (happ_err_prob): the rounding errors of round-to-nearest
+// operations and the hardware functions' deviations from their mean are
+// modelled as independent, zero-mean and bounded by the same amounts;
+// Hoeffding's inequality then bounds their sum by lambda times the root of
+// the sum of the squared bounds with probability at least
+// 1 - 2 exp(-lambda^2 / 2) (lambda = 8: 2.5e-14 per estimate).  The lane
+// sums' roundings u32 S_j (S_j a partial sum) have sum of squares at most
+// 1024 sum t^2 (S_j <= S_32, S_32^2 <= 32 sum t^2 over the lane) and
+// 528 sum g^2 for the signed g terms; with mean t^2 <= 2 + 2 ln^2 2 and
+// g^2 <= 1/e this gives
+//   dE1 <= u32 (ln 2 bL + bE + 8 sqrt(3158 / n)),
+//   dE2 <= u32 (e^-1/2 bE + 8 sqrt(223 / n)),
+// where bE = LINGAM_EXP2_BIAS and bL = LINGAM_LOG2_BIAS bound the hardware
+// functions' systematic error (the largest mean error within a binade,
+// measured by lingam_check_terms) and stay additive.
 // Eq. (HApp) then moves by at most
 //   2 k1 |E1 - beta| dE1 + 3 k1 dE1^2 + 2 k2 |E2| dE2 + 3 k2 dE2^2
 // (E1, E2 the computed means; the factor 3 absorbs using them in place of the
 // exact ones).
-// d_in (in units of u32) adds an error of the arguments themselves to both
-// moments: with binary32 rows (FP32 storage) a residual u = s (z_v - b z_w)
-// is formed by one binary32 fma from rows stored to u32 and b rounded to
-// binary32, which moves it by at most u32 s (|z_v| + 2 |z_w|) beyond its own
-// rounding; both term derivatives are at most 1 in magnitude and the rows
-// have unit variance (mean |z| <= 1), so each moment moves by at most
-// 3 s u32 more: d_in = 3 s.  (0 for a variable's own entropy and for
-// residuals formed in binary64.)
-__device__ __forceinline__ double happ_err_mixed(double s_lc, double s_g, double n, double d_in = 0.0) {
-  constexpr double U32 = 5.9604644775390625e-08;
-  const double E1 = s_lc / n - LN2;
-  const double E2 = s_g / n;
-  const double d1 = U32 * (32.0 * (s_lc / n) + 11.6 + d_in);
-  const double d2 = U32 * (25.4 + d_in);
-  return 2.0 * K1 * fabs(E1 - BETA) * d1 + 3.0 * K1 * d1 * d1 + 2.0 * K2 * fabs(E2) * d2 +
-         3.0 * K2 * d2 * d2;
+//
+// s_in (FP32 storage only, else 0) is the residual's scale 1/sqrt(1 - b^2):
+// a residual u = s (z_v - b z_w) formed by one binary32 fma from rows stored
+// to u32 and b rounded to binary32 moves by at most u32 s (|z_v| + 2 |z_w|)
+// beyond its own rounding; both term derivatives are at most 1 in magnitude
+// and mean |z| <= 1, so each moment moves by at most 3 s u32 more in the
+// worst case.  In the probable bound the rounding of b is one error shared
+// by all samples (s u32, additive) and the storage and fma roundings are
+// per-sample (3 s u32 each, under the square root).
+constexpr double U32 = 5.9604644775390625e-08;
+constexpr double HOEFFDING_LAMBDA = 8.0;
+
+__device__ __forceinline__ double happ_move(double E1, double E2, double d1, double d2) {
+  return 2.0 * K1 * fabs(E1 - BETA) * d1 + 3.0 * K1 * d1 * d1 + 2.0 * K2 * fabs(E2) * d2 + 3.0 * K2 * d2 * d2;
+}
+
+__device__ __forceinline__ double happ_err_mixed(double s_lc, double s_g, double n, double s_in = 0.0) {
+  constexpr double E = LINGAM_EXP2_ERR, L = LINGAM_LOG2_ERR, G = 0.60653065971263342;  // e^-1/2
+  const double d1 = U32 * (32.0 * (s_lc / n) + 3.0 + 2.10 + E + LN2 * L + 3.0 * s_in);
+  const double d2 = U32 * (32.0 * G + (1.0 + E) * G + 2.9 + 3.0 * s_in);
+  return happ_move(s_lc / n - LN2, s_g / n, d1, d2);
+}
+
+__device__ __forceinline__ double happ_err_prob(double s_lc, double s_g, double n, double s_in = 0.0) {
+  constexpr double bE = LINGAM_EXP2_BIAS, bL = LINGAM_LOG2_BIAS, G = 0.60653065971263342;
+  const double r1 = 3158.0 + 9.0 * s_in * s_in, r2 = 223.0 + 9.0 * s_in * s_in;
+  const double d1 = U32 * (LN2 * bL + bE + s_in + HOEFFDING_LAMBDA * sqrt(r1 / n));
+  const double d2 = U32 * (G * bE + s_in + HOEFFDING_LAMBDA * sqrt(r2 / n));
+  return happ_move(s_lc / n - LN2, s_g / n, d1, d2);
 }
 
 __device__ __forceinline__ double happ_from_sums(double s_lc, double s_g, double n) {
@@ -556,6 +591,7 @@ __device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma
       }
       H[blockIdx.x] = happ_from_sums(lc, g, (double)n);
       eH[blockIdx.x] = MIXED ? happ_err_mixed(lc, g, (double)n) : 0.0;
+      d.eHp[blockIdx.x] = MIXED ? happ_err_prob(lc, g, (double)n) : 0.0;
     }
     return;
   }
@@ -600,6 +636,7 @@ __device__ __forceinline__ void k_entropy_body(const Dev& d, int t, double gamma
   if (threadIdx.x == 0) {
     H[blockIdx.x] = happ_from_sums(lc, g, (double)n);
     eH[blockIdx.x] = MIXED ? happ_err_mixed(lc, g, (double)n) : 0.0;
+    d.eHp[blockIdx.x] = MIXED ? happ_err_prob(lc, g, (double)n) : 0.0;
   }
 }
 
@@ -714,6 +751,7 @@ __device__ __forceinline__ void pair_item(const Dev& d, int t, const BandArgs& a
   uint8_t* __restrict__ pend = d.pend;
   const int32_t* __restrict__ idx = d.idx[buf];
   Ctl* ctl = d.ctl;
+  const int messaging = d.messaging;
   constexpr int WPR = TB / TPW;     // waves per row
   constexpr int NW = RG * WPR;      // waves per work-group
   constexpr int SPL = PS / 64;      // samples per lane and stage
@@ -746,7 +784,10 @@ __device__ __forceinline__ void pair_item(const Dev& d, int t, const BandArgs& a
       if (w >= r || w == v) continue;
       if (!__builtin_isnan(M[(int64_t)v * p + w])) continue;
       const bool w_row = alive[w] != 0 && v_in_targets;  // w also a row of this band
-      if (!w_row || v < w) mask |= 1u << j;
+      // messaging (Sec. 3.1): a pair both of whose variables are rows of the
+      // band is evaluated once, by the lower position; without it every row
+      // evaluates its own direction
+      if (!w_row || v < w || !messaging) mask |= 1u << j;
     }
   }
   mask = __builtin_amdgcn_readfirstlane(mask);
@@ -903,13 +944,13 @@ __device__ __forceinline__ void pair_item(const Dev& d, int t, const BandArgs& a
     if (mask >> j & 1u) {
       const int w = B * TB + j0 + j;
       P[(((int64_t)chunk * p + v) * p + w) * 4 + c] = tot;
-      P[(((int64_t)chunk * p + w) * p + v) * 4 + ((c + 2) & 3)] = tot;
+      if (messaging) P[(((int64_t)chunk * p + w) * p + v) * 4 + ((c + 2) & 3)] = tot;
     }
   }
   if (chunk == 0 && lane < TPW && (mask >> lane & 1u)) {
     const int w = B * TB + j0 + lane;
     pend[(int64_t)v * p + w] = 1;
-    pend[(int64_t)w * p + v] = 1;
+    if (messaging) pend[(int64_t)w * p + v] = 1;   // the reverse test is the negation
   }
   if (chunk == 0 && mask) {
     n_eval += (unsigned)__popc(mask);
@@ -972,24 +1013,25 @@ __device__ __forceinline__ int band_items(const Dev& d, int t) {
 // Device work queue over the data sets of a batch.  The grid is persistent
 // (about the work-groups the device holds at once) and not tied to any data
 // set: a work-group claims QCLAIM items of one data set at a time from that
-// set's claim counter (Ctl::q_next), and when its set has no items left it
-// looks, from its set onward, for the next set that still has some.  Small
-// or finished data sets therefore occupy no work-groups, and the last live
-// sets of an uneven batch get the whole device.  (Counters start at 0 with
-// each band: the iteration set-up and every band decision reset them.)
-constexpr int QCLAIM = 2;
+// set's claim counter (Ctl::q_next), first from the set it worked on last,
+// and when that set has no items left it looks, from that set onward, for
+// the next set that still has some.  Small or finished data sets therefore
+// occupy no work-groups, and the last live sets of an uneven batch get the
+// whole device.  The host passes the sets that still have an iteration at
+// t (act[0, nact), in order of the iteration they end at, latest first), so
+// the search skips the finished ones.  (Counters start at 0 with each band:
+// the iteration set-up and every band decision reset them.)
+constexpr int QCLAIM = 4;
 
-template <int RG>
-__device__ int claim_set(const Dev* __restrict__ devs, int count, int t, int start, int* sh_best) {
-  // every thread checks its share of the sets in rotation order from
-  // `start`; the first with unclaimed items wins
+// The first set, in rotation order from position `start` of act, for which
+// has_work(set) holds; -1 if none.  All threads of the group take part.
+template <class F>
+__device__ int find_set(const int32_t* __restrict__ act, int nact, int start, int* sh_best, F has_work) {
   if (threadIdx.x == 0) *sh_best = 0x7fffffff;
   __syncthreads();
-  for (int off = threadIdx.x; off < count; off += blockDim.x) {
-    const int k = (start + off) % count;
-    const Dev& d = devs[k];
-    const int items = band_items<RG>(d, t);
-    if (items > 0 && (int)__atomic_load_n(&d.ctl->q_next, __ATOMIC_RELAXED) < items) {
+  for (int off = threadIdx.x; off < nact; off += blockDim.x) {
+    const int pos = (start + off) % nact;
+    if (has_work(act[pos])) {
       atomicMin(sh_best, off);
       break;
     }
@@ -997,11 +1039,12 @@ __device__ int claim_set(const Dev* __restrict__ devs, int count, int t, int sta
   __syncthreads();
   const int best = *sh_best;
   __syncthreads();
-  return best == 0x7fffffff ? -1 : (start + best) % count;
+  return best == 0x7fffffff ? -1 : (start + best) % nact;
 }
 
 template <bool MIXED, int RG, int TPW, int PS, typename S>
-__device__ __forceinline__ void k_pair_queue_body(const Dev* __restrict__ devs, int count, int t, BandArgs a) {
+__device__ __forceinline__ void k_pair_queue_body(const Dev* __restrict__ devs, const int32_t* __restrict__ act,
+                                                  int nact, int count, int t, BandArgs a) {
   constexpr int NW = RG * (TB / TPW);
   __shared__ int s_best, s_i0, s_cnt, s_m, s_tb0, s_ntb;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
@@ -1010,7 +1053,8 @@ __device__ __forceinline__ void k_pair_queue_body(const Dev* __restrict__ devs, 
   // previous score launch has ended, and the next starts after this one)
   if (blockIdx.x == 0)
     for (int k = threadIdx.x; k < count; k += blockDim.x) devs[k].ctl->q_rows = 0;
-  int cur = (int)((int64_t)blockIdx.x * count / gridDim.x);
+  if (nact < 1) return;
+  int pos = (int)((int64_t)blockIdx.x * nact / gridDim.x);
   int cur_set = -1;
   unsigned n_eval = 0, n_comp = 0;
   auto flush = [&](int k) {
@@ -1021,13 +1065,25 @@ __device__ __forceinline__ void k_pair_queue_body(const Dev* __restrict__ devs, 
     }
     n_eval = n_comp = 0;
   };
+  auto has_items = [&](int k) {
+    const Dev& d = devs[k];
+    const int items = band_items<RG>(d, t);
+    return items > 0 && (int)__atomic_load_n(&d.ctl->q_next, __ATOMIC_RELAXED) < items;
+  };
+  bool fresh = true;   // pos has not been tried since it was chosen
   for (;;) {
-    const int k = claim_set<RG>(devs, count, t, cur, &s_best);
-    if (k < 0) break;
+    if (!fresh) {
+      pos = find_set(act, nact, pos, &s_best, has_items);
+      if (pos < 0) break;
+    }
+    fresh = false;
+    const int k = act[pos];
     if (threadIdx.x == 0) {
       const Dev& d = devs[k];
       const int items = band_items<RG>(d, t);
-      const int i0 = (int)atomicAdd(&d.ctl->q_next, (uint32_t)QCLAIM);
+      int i0 = items;
+      if (items > 0 && (int)__atomic_load_n(&d.ctl->q_next, __ATOMIC_RELAXED) < items)
+        i0 = (int)atomicAdd(&d.ctl->q_next, (uint32_t)QCLAIM);
       s_i0 = i0;
       s_cnt = i0 < items ? min(QCLAIM, items - i0) : 0;
       s_m = d.ctl->n_alive;
@@ -1037,8 +1093,8 @@ __device__ __forceinline__ void k_pair_queue_body(const Dev* __restrict__ devs, 
     __syncthreads();
     const int i0 = s_i0, cnt = s_cnt, m = s_m, tb0 = s_tb0, ntb = s_ntb;
     __syncthreads();
-    cur = k;
-    if (cnt == 0) continue;   // another group took the last items: look again
+    if (cnt == 0) continue;   // this set is exhausted: look for another
+    fresh = true;             // try the same set again next
     if (k != cur_set) {
       flush(cur_set);
       cur_set = k;
@@ -1062,9 +1118,10 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(const Dev* _
 
 // The batch form: one persistent grid over the device work queue.
 template <bool MIXED, int RG, int TPW, int PS, typename S>
-__global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_queue(const Dev* __restrict__ devs, int count,
-                                                                    int t, BandArgs a) {
-  k_pair_queue_body<MIXED, RG, TPW, PS, S>(devs, count, t, a);
+__global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_queue(const Dev* __restrict__ devs,
+                                                                    const int32_t* __restrict__ act, int nact,
+                                                                    int count, int t, BandArgs a) {
+  k_pair_queue_body<MIXED, RG, TPW, PS, S>(devs, act, nact, count, t, a);
 }
 
 // Work-group shapes of the pair kernel (results do not depend on them;
@@ -1123,7 +1180,7 @@ static void launch_pair_shape(const Batch& b, int t, const BandArgs& a, int ntb_
     // the persistent grid: the work-groups the device holds at once
     const int gq = (resident_groups<MIXED, RG, TPW, PS, S>() + 7) / 8 * 8;
     hipExtLaunchKernelGGL((k_pair_queue<MIXED, RG, TPW, PS, S>), dim3(gq), blk, 0, s, ev0, ev1, 0,
-                          (const Dev*)b.dd, b.count, t, a);
+                          (const Dev*)b.dd, b.act, b.active_at(t), b.count, t, a);
   } else {
     hipExtLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS, true, S>), g, blk, 0, s, ev0, ev1, 0,
                           (const Dev*)b.dd, b.one, t, a);
@@ -1335,10 +1392,12 @@ __device__ __forceinline__ void score_row(const Dev& d, int t, int x) {
   const int mixed = d.mixed, store32 = d.store32;
   const double* __restrict__ dsc = d.dsc[buf];
   double* __restrict__ Meps = d.Meps;
+  double* __restrict__ Mepsp = d.Mepsp;
   const double* __restrict__ eH = d.eH;
+  const double* __restrict__ eHp = d.eHp;
   __shared__ double sh[4];
   __shared__ int shi[4];
-  double s = 0.0, es = 0.0;
+  double s = 0.0, es = 0.0, esp = 0.0;
   int incomplete = 0;
   const double hx = H[x];
   const double* sig = d.Sig[buf] + (int64_t)x * p;
@@ -1350,7 +1409,7 @@ __device__ __forceinline__ void score_row(const Dev& d, int t, int x) {
     // pending test needs a second, dependent fetch (its chunk partials)
     const int64_t o = (int64_t)x * p + w;
     const uint8_t pd = pend[o];
-    double mv = M[o], ev = mixed ? Meps[o] : 0.0;
+    double mv = M[o], ev = mixed ? Meps[o] : 0.0, evp = mixed ? Mepsp[o] : 0.0;
     if (pd) {
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       for (int c = 0; c < nchunk; ++c) {
@@ -1363,16 +1422,18 @@ __device__ __forceinline__ void score_row(const Dev& d, int t, int x) {
       M[o] = mv;
       pend[o] = 0;
       if (mixed) {
-        double din = 0.0;
+        double sin = 0.0;
         if (store32) {
           const double b = sig[w] * (dx * dsc[w]);   // as the pair kernel forms it
-          din = 3.0 / sqrt(1.0 - b * b);
+          sin = 1.0 / sqrt(1.0 - b * b);
         }
-        ev = (eH[x] + eH[w]) + (happ_err_mixed(a0, a1, n, din) + happ_err_mixed(a2, a3, n, din));
+        ev = (eH[x] + eH[w]) + (happ_err_mixed(a0, a1, n, sin) + happ_err_mixed(a2, a3, n, sin));
+        evp = (eHp[x] + eHp[w]) + (happ_err_prob(a0, a1, n, sin) + happ_err_prob(a2, a3, n, sin));
         Meps[o] = ev;
+        Mepsp[o] = evp;
       }
     } else if (__builtin_isnan(mv)) {
-      ev = 0.0;   // not evaluated (its bound slot holds an earlier iteration's value)
+      ev = evp = 0.0;   // not evaluated (its bound slots hold an earlier iteration's values)
     }
     if (__builtin_isnan(mv)) {
       incomplete = 1;
@@ -1380,14 +1441,19 @@ __device__ __forceinline__ void score_row(const Dev& d, int t, int x) {
       const double neg = mv < 0.0 ? mv : 0.0;
       s += neg * neg;
       if (mv < ev) es += 2.0 * (-neg) * ev + 3.0 * ev * ev;
+      if (mv < evp) esp += 2.0 * (-neg) * evp + 3.0 * evp * evp;
     }
   }
   s = block_sum256(s, sh);
-  if (mixed) es = block_sum256(es, sh);
+  if (mixed) {
+    es = block_sum256(es, sh);
+    esp = block_sum256(esp, sh);
+  }
   incomplete = block_or256(incomplete, shi);
   if (threadIdx.x == 0) {
     d.S[x] = s;
     d.eT[x] = es;
+    d.eTp[x] = esp;
     d.complete[x] = incomplete ? 0 : 1;
   }
 }
@@ -1487,44 +1553,34 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a, do
 }
 
 // A batch on the device work queue: work-groups claim rows of any data set
-// (Ctl::q_rows) and count each finished row in (Ctl::arrivals, released
-// after the row's scores); the group that finishes a set's last row takes
-// that set's decision.
-template <int RG>
-__device__ int claim_score_set(const Dev* __restrict__ devs, int count, int t, int start, int* sh_best) {
-  if (threadIdx.x == 0) *sh_best = 0x7fffffff;
-  __syncthreads();
-  for (int off = threadIdx.x; off < count; off += blockDim.x) {
-    const int k = (start + off) % count;
-    const Dev& d = devs[k];
-    const Ctl* c = d.ctl;
-    if (rows_left(d, t) < 2 || halted(c) || c->done) continue;
-    const int rows = (min(rows_left(d, t), (c->tb_next + c->ntb_next) * TB) - c->tb_next * TB) + c->n_alive;
-    if ((int)__atomic_load_n(&c->q_rows, __ATOMIC_RELAXED) < rows) {
-      atomicMin(sh_best, off);
-      break;
-    }
-  }
-  __syncthreads();
-  const int best = *sh_best;
-  __syncthreads();
-  return best == 0x7fffffff ? -1 : (start + best) % count;
-}
-
-__device__ __forceinline__ void k_score_queue_body(const Dev* __restrict__ devs, int count, int t, BandArgs a,
-                                                   double gamma_mult) {
+// (Ctl::q_rows), first of the set they worked on last, and count each
+// finished row in (Ctl::arrivals, released after the row's scores); the
+// group that finishes a set's last row takes that set's decision.
+__device__ __forceinline__ void k_score_queue_body(const Dev* __restrict__ devs, const int32_t* __restrict__ act,
+                                                   int nact, int t, BandArgs a, double gamma_mult) {
   __shared__ int s_best, s_q, s_last;
   __shared__ BandRows s_br;
-  int cur = (int)((int64_t)blockIdx.x * count / gridDim.x);
-  for (;;) {
-    const int k = claim_score_set<1>(devs, count, t, cur, &s_best);
-    if (k < 0) break;
-    cur = k;
+  if (nact < 1) return;
+  auto has_rows = [&](int k) {
     const Dev& d = devs[k];
+    const Ctl* c = d.ctl;
+    if (rows_left(d, t) < 2 || halted(c) || c->done) return false;
+    const int rows = (min(rows_left(d, t), (c->tb_next + c->ntb_next) * TB) - c->tb_next * TB) + c->n_alive;
+    return (int)__atomic_load_n(&c->q_rows, __ATOMIC_RELAXED) < rows;
+  };
+  int pos = (int)((int64_t)blockIdx.x * nact / gridDim.x);
+  bool fresh = true;
+  for (;;) {
+    if (!fresh) {
+      pos = find_set(act, nact, pos, &s_best, has_rows);
+      if (pos < 0) break;
+    }
+    fresh = false;
+    const Dev& d = devs[act[pos]];
     if (threadIdx.x == 0) {
       // a claim below the row count holds the set's band open (its decision
       // waits for this row), so its band fields read after it are stable
-      s_q = (int)atomicAdd(&d.ctl->q_rows, 1u);
+      s_q = has_rows(act[pos]) ? (int)atomicAdd(&d.ctl->q_rows, 1u) : 0x7fffffff;
       s_br = band_rows(d, t);
     }
     __syncthreads();
@@ -1532,6 +1588,7 @@ __device__ __forceinline__ void k_score_queue_body(const Dev* __restrict__ devs,
     const int qrow = s_q;
     __syncthreads();
     if (qrow >= br.rows) continue;
+    fresh = true;
     const int x = band_row(d, br, qrow);
     if (x >= 0) score_row(d, t, x);
     __syncthreads();
@@ -1557,9 +1614,9 @@ __global__ __launch_bounds__(256) void k_score(const Dev* __restrict__ devs, con
     k_score_body(one, t, a, gamma_mult);
 }
 
-__global__ __launch_bounds__(256) void k_score_queue(const Dev* __restrict__ devs, int count, int t, BandArgs a,
-                                                     double gamma_mult) {
-  k_score_queue_body(devs, count, t, a, gamma_mult);
+__global__ __launch_bounds__(256) void k_score_queue(const Dev* __restrict__ devs, const int32_t* __restrict__ act,
+                                                     int nact, int t, BandArgs a, double gamma_mult) {
+  k_score_queue_body(devs, act, nact, t, a, gamma_mult);
 }
 
 hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_mult, int dense, int ntb_hint,
@@ -1578,9 +1635,10 @@ hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_m
                                                                     dev) != hipSuccess || cus < 1)
         cus = 256;
     }
-    const int rows_all = (std::min(r, std::max(1, std::min(ntb_hint, nb)) * TB) + r) * b.count;
-    hipLaunchKernelGGL(k_score_queue, dim3(std::max(8, std::min(4 * cus, rows_all))), dim3(256), 0, s,
-                       (const Dev*)b.dd, b.count, t, a, gamma_mult);
+    const int nact = b.active_at(t);
+    const int rows_act = (std::min(r, std::max(1, std::min(ntb_hint, nb)) * TB) + r) * std::max(nact, 1);
+    hipLaunchKernelGGL(k_score_queue, dim3(std::max(8, std::min(4 * cus, rows_act))), dim3(256), 0, s,
+                       (const Dev*)b.dd, b.act, nact, t, a, gamma_mult);
     return hipGetLastError();
   }
   const int rows = std::min(r, std::max(1, std::min(ntb_hint, nb)) * TB) + r;
@@ -1661,6 +1719,7 @@ __device__ __forceinline__ void k_finish_iter_body(const Dev& d, int t) {
     Tstate[o] = complete[y] ? 1 : 2;
     Hall[o] = H[y];
     Terr[o] = eT[y];
+    d.Terrp[o] = d.eTp[y];
   }
   if (threadIdx.x == 0) {
     order[t] = idx[ctl->root];
@@ -1921,6 +1980,7 @@ __device__ __forceinline__ void k_last_body(const Dev& d, int t) {
   Tall[(int64_t)t * p + idx[0]] = 0.0;
   Tstate[(int64_t)t * p + idx[0]] = 1;
   Terr[(int64_t)t * p + idx[0]] = 0.0;
+  d.Terrp[(int64_t)t * p + idx[0]] = 0.0;
 }
 
 __global__ void k_last(const Dev* __restrict__ devs, const Dev one, int t) {
@@ -2062,6 +2122,73 @@ hipError_t launch_estimate_B(const Dev& d, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_unit_inverse_col, dim3(p), dim3(256), sizeof(double) * p, s, d);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Self-check of the hardware binary32 exp2 / log2 that the mixed-precision
+// rounding bound assumes
+// ============================================================================
+// Every binary32 argument of the two ranges the per-sample terms use is
+// evaluated with the hardware instruction and with the binary64 library
+// function (about 2^-52 relative, so its own error is negligible at binary32
+// scale): v_exp_f32 over x in [-126, 0] (normal results; below, the term is
+// under 2^-126 absolutely) as a relative error, v_log_f32 over [1, 2] as an
+// absolute error, both in units of u32 = 2^-24.  Per range: the largest
+// error, the sum of signed errors (for the mean), and per binade of the
+// argument the sum of signed errors (to bound a systematic bias that a
+// data set concentrated in one binade would see).
+// Bit patterns are taken in aligned chunks of 2^16 (never across a binade:
+// a binade holds 2^23), one chunk per work-group at a time.
+constexpr uint32_t SWEEP_CHUNK = 1u << 16;
+
+__global__ __launch_bounds__(256) void k_term_sweep(TermSweep* out, int which, uint32_t lo, uint32_t hi) {
+  __shared__ double sh_max[256], sh_sum[256];
+  for (uint64_t c0 = (uint64_t)lo + (uint64_t)blockIdx.x * SWEEP_CHUNK; c0 <= hi;
+       c0 += (uint64_t)gridDim.x * SWEEP_CHUNK) {
+    const uint64_t c1 = min((uint64_t)hi, c0 + SWEEP_CHUNK - 1);
+    double mx = 0.0, sm = 0.0;
+    for (uint64_t b = c0 + threadIdx.x; b <= c1; b += 256) {
+      const float a = __uint_as_float((uint32_t)b);
+      double err;
+      if (which == 0) {
+        const float x = -a;                         // [-126, 0]
+        const double ref = exp2((double)x);
+        err = ((double)__builtin_amdgcn_exp2f(x) - ref) / ref * 16777216.0;
+      } else {
+        const double ref = log2((double)a);         // [1, 2]
+        err = ((double)__builtin_amdgcn_logf(a) - ref) * 16777216.0;
+      }
+      mx = fmax(mx, fabs(err));
+      sm += err;
+    }
+    sh_max[threadIdx.x] = mx;
+    sh_sum[threadIdx.x] = sm;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) {
+        sh_max[threadIdx.x] = fmax(sh_max[threadIdx.x], sh_max[threadIdx.x + s]);
+        sh_sum[threadIdx.x] += sh_sum[threadIdx.x + s];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      atomicMax(&out->max_bits[which], (unsigned long long)__double_as_longlong(sh_max[0]));
+      atomicAdd(&out->sum[which], sh_sum[0]);
+      const int binade = which == 0 ? (int)((c0 >> 23) & 0xff) : 0;   // exponent field of |x|
+      if (binade < 160) atomicAdd(&out->binade_sum[which][binade], sh_sum[0]);
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_term_sweep(TermSweep* out, hipStream_t s) {
+  const uint32_t exp_hi = 0x42FC0000u;   // 126.0f
+  const uint32_t log_lo = 0x3F800000u, log_hi = 0x40000000u;   // 1.0f, 2.0f
+  hipLaunchKernelGGL(k_term_sweep, dim3(2048), dim3(256), 0, s, out, 0, 0u, exp_hi);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_term_sweep, dim3(128), dim3(256), 0, s, out, 1, log_lo, log_hi);
   return hipGetLastError();
 }
 

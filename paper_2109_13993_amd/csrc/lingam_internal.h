@@ -86,6 +86,8 @@ struct Dev {
   // so that their atomics do not queue on one address: [0, PAIR_SLOTS)
   // evaluated pairs, [PAIR_SLOTS, 2 PAIR_SLOTS) pairs computed.  Summed by the host.
   unsigned long long* pair_slots = nullptr;
+  int messaging = 1;         // 1 = a pair's reverse test is its negation (Sec. 3.1); 0 = each
+                             // direction evaluated by its own row (ablation)
   int band_k0 = 4;           // target blocks of an iteration's first band (every block: no threshold)
   int band_adapt = 1;        // 1 = size later bands from the alive count, 0 = band_k0 blocks each
   int64_t ldz = 0;           // row stride of Z (elements), multiple of SUB
@@ -120,6 +122,12 @@ struct Dev {
   double* Meps = nullptr;    // p x p rounding bound of each evaluated test (mixed mode)
   double* eT = nullptr;      // [p] rounding bound of each score (mixed mode)
   double* Terr = nullptr;    // [p*p] eT per iteration, by original index
+  // the probable bounds (independent rounding errors, Hoeffding) beside the
+  // worst-case ones: per H, per test, per score, per iteration
+  double* eHp = nullptr;
+  double* Mepsp = nullptr;
+  double* eTp = nullptr;
+  double* Terrp = nullptr;
   double* M = nullptr;       // p x p test matrix of the iteration (NaN = not evaluated)
   double* S = nullptr;       // [p] scores (sum of min(0, M)^2 over evaluated pairs)
   uint8_t* alive = nullptr;  // [p] S <= gamma at the last snapshot
@@ -184,6 +192,19 @@ struct Batch {
   int mixed = 0;
   int store32 = 0;           // rows stored in binary32 (every data set of the batch)
   int queue = 1;             // batches: pair and score work on the device work queue
+  // Sets that have an iteration at t: act[0, active_at(t)) on the device;
+  // act_until[i] (host, descending) is the first iteration set act[i] no
+  // longer has.
+  const int32_t* act = nullptr;
+  const int* act_until = nullptr;
+  int active_at(int t) const {
+    int lo = 0, hi = count;   // act_until is descending: count the entries > t
+    while (lo < hi) {
+      const int mid = (lo + hi) / 2;
+      if (act_until[mid] > t) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  }
 };
 
 // ---- launch wrappers (kernels.hip) --------------------------------------
@@ -217,6 +238,15 @@ hipError_t launch_resume(const Batch& b, hipStream_t s);
 hipError_t launch_gather(const double* X, int64_t n_src, int64_t p, const int64_t* idx, int64_t n_idx,
                          double* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
+// Hardware binary32 exp2 / log2 against binary64 over every argument of the
+// ranges the mixed-precision terms use (errors in units of u32 = 2^-24):
+// [0] v_exp_f32 on [-126, 0] (relative), [1] v_log_f32 on [1, 2] (absolute).
+struct TermSweep {
+  unsigned long long max_bits[2];  // largest |error| (bit pattern of a non-negative double)
+  double sum[2];                   // sum of signed errors
+  double binade_sum[2][160];       // exp2: per exponent field of |x|; log2: [0] only
+};
+hipError_t launch_term_sweep(TermSweep* out, hipStream_t s);
 // C0 from the first Gram (after launch_gram at t = 0).
 hipError_t launch_corr_snapshot(const Dev& d, hipStream_t s);
 // B from C0 and the causal order in d.order (host-side descriptor d).

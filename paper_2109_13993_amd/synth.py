@@ -161,3 +161,43 @@ def paper_scalability_dataset(p: int, n: int, dense: bool, rng) -> Dataset:
     inv[perm] = np.arange(p)
     return Dataset(X=np.ascontiguousarray(X_gen[perm]), B=B_gen[np.ix_(perm, perm)],
                    true_order=inv.astype(np.int32), perm=perm, noise=np.full(p, -1))
+
+
+# ---- stand-ins for the paper's metabolic-flux data sets (Sec. 5.2) ---------------
+
+# p of the real data sets of the paper's Table 1 (their n is 10000)
+FLUX_P = {"ecoli_core": 85, "iJR904": 770, "iAF1260b": 1588, "iAF1260": 1633, "iY75_1357": 2249,
+          "iECDH10B_1368": 2252, "iML1515": 2326, "iEC1372_W3110": 2339}
+
+
+def flux_like_dataset(p: int, n: int, rng, noise: float = 1e-3, met_frac: float = 0.4) -> Dataset:
+    """Rows shaped like sampled fluxes of a metabolic network: the p
+    reactions' flux samples lie (up to relative `noise`) in the null space of
+    a sparse stoichiometric-like matrix S (m = met_frac p metabolites; each
+    reaction consumes or produces 1 to 3 of them with coefficients in
+    {+-1, +-2}).  v = N z, N an orthonormal basis of null(S) and z
+    non-Gaussian (uniform) coordinates, so the variables are strongly and
+    jointly collinear; with noise = 0 they are exactly linearly dependent
+    (p - rank S degrees of freedom, and reactions outside every null vector
+    carry no flux at all), which the search must report as degenerate.
+    The real data sets are not available; only their shape (p, n) and the
+    collinearity of steady-state fluxes are reproduced."""
+    m = max(1, int(round(met_frac * p)))
+    S = np.zeros((m, p))
+    for j in range(p):
+        k = int(rng.integers(1, 4))
+        rows = rng.choice(m, size=k, replace=False)
+        S[rows, j] = rng.choice(np.array([-2.0, -1.0, 1.0, 2.0]), size=k)
+    _, sv, Vt = np.linalg.svd(S, full_matrices=True)
+    rank = int(np.sum(sv > 1e-10 * sv[0]))
+    N = Vt[rank:].T                                   # p x (p - rank), orthonormal
+    z = rng.uniform(-np.sqrt(3.0), np.sqrt(3.0), (N.shape[1], n))
+    X = N @ z
+    if noise > 0:
+        # blocked reactions (rows that are zero in the null space) get noise
+        # at the scale of a typical row
+        sd = X.std(axis=1, keepdims=True)
+        sd = np.maximum(sd, np.median(sd))
+        X += noise * sd * rng.laplace(0.0, 1.0 / np.sqrt(2.0), (p, n))
+    return Dataset(X=np.ascontiguousarray(X), B=np.zeros((p, p)), true_order=np.arange(p, dtype=np.int32),
+                   perm=np.arange(p), noise=np.full(p, -1))

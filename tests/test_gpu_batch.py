@@ -29,6 +29,7 @@ def _same(b, s, tag):
     assert both.any(axis=1)[:int((s.order >= 0).sum()) - 1].all(), tag
     assert np.array_equal(b.T[both], s.T[both]), tag          # bitwise
     assert np.array_equal(b.T_err[both], s.T_err[both]), tag
+    assert np.array_equal(b.T_err_prob[both], s.T_err_prob[both]), tag
 
 
 def _mixed_batch(seed):

@@ -125,6 +125,47 @@ def test_threshold_keeps_order_and_complete_scores():
                 assert on.pairs_evaluated < off.pairs_evaluated
 
 
+def test_messaging_off_gives_the_same_results_with_twice_the_pairs():
+    # without messaging every variable evaluates its own direction of each
+    # pair (Sec. 3.1 ablation): the same order and bitwise the same scores,
+    # with every pair evaluated twice when nothing is pruned
+    for seed, (p, n) in enumerate([(27, 3001), (60, 4000)]):
+        ds = synth.lingam_dataset(p, n, 0.3, "mixed", rng=np.random.default_rng(70 + seed))
+        for precision in ("fp64", "mixed"):
+            on = lg.fit_order(ds.X, precision=precision, use_threshold=False, record_M_iters=2)
+            off = lg.fit_order(ds.X, precision=precision, use_threshold=False, record_M_iters=2, messaging=False)
+            assert np.array_equal(on.order, off.order)
+            assert np.array_equal(on.T, off.T, equal_nan=True) and np.array_equal(on.M, off.M, equal_nan=True)
+            assert off.pairs_evaluated == 2 * on.pairs_evaluated == (p + 1) * p * (p - 1) // 3
+            th = lg.fit_order(ds.X, precision=precision, messaging=False, band_blocks=1)
+            assert np.array_equal(th.order, on.order)
+            comp = th.T_state == 1
+            assert np.array_equal(th.T[comp], on.T[comp])
+            _log("p=%d %s messaging off: %d pairs with the threshold, %d without" % (
+                p, precision, th.pairs_evaluated, off.pairs_evaluated))
+
+
+def test_flux_like_stand_in():
+    # data shaped like sampled metabolic fluxes (rows near the null space of
+    # a sparse stoichiometric-like matrix, E. coli core's p = 85): the FP64
+    # order equals the oracle's; exactly collinear rows must end DEGENERATE
+    # in both
+    ds = synth.flux_like_dataset(85, 10000, np.random.default_rng(85))
+    o = oracle.fit_order(ds.X, pair_once=True)
+    g = lg.fit_order(ds.X, precision="fp64")
+    assert list(g.order) == list(o["order"])
+    gm = lg.fit_order(ds.X, precision="mixed")
+    _log("flux-like p=85: mixed order %s the oracle's" % ("equals" if np.array_equal(gm.order, o["order"])
+                                                         else "differs from"))
+    ex = synth.flux_like_dataset(85, 2000, np.random.default_rng(86), noise=0.0)
+    with pytest.raises(oracle.OracleError) as eo:
+        oracle.fit_order(ex.X, pair_once=True)
+    assert eo.value.status == oracle.E_DEGENERATE
+    with pytest.raises(lg.LingamError) as e:
+        lg.fit_order(ex.X, precision="fp64")
+    assert e.value.status == lg.E_DEGENERATE
+
+
 @pytest.fixture(scope="module")
 def cfg2():
     ds = synth.config_dataset(2)   # p=100, n=10000
@@ -360,6 +401,35 @@ def test_fp32_storage_scores_and_order(cfg2):
     assert diff.size == 0
     # half the row storage of the binary64 modes
     assert lg.workspace_size(10000, 100, "fp32_storage") < lg.workspace_size(10000, 100, "mixed")
+
+
+def test_probable_bound_holds_and_certifies(cfg2):
+    # the probable bound (independent rounding errors, Hoeffding) against
+    # the FP64 oracle, teacher-forced: every score within it, and it
+    # certifies more iterations than the worst-case bound, none wrongly
+    ds, o = cfg2
+    p = ds.X.shape[0]
+    for precision in ("mixed", "fp32_storage"):
+        g = lg.fit_order(ds.X, precision=precision, use_threshold=False, forced_order=o["order"])
+        fin = np.isfinite(o["T"])
+        dT = np.abs(g.T[fin] - o["T"][fin])
+        tol64 = 1e-9 * np.abs(o["T"][fin]) + 1e-12
+        if precision == "mixed":     # binary64 rows: the same data, so every score is covered
+            ratio = dT / (g.T_err_prob[fin] + tol64)
+            assert ratio.max() <= 1.0, ratio.max()
+        cw = cp = 0
+        for t in range(p - 1):
+            top, ok = _gap_certified(g.T, g.T_err, g.T_state, t)
+            top_p, ok_p = _gap_certified(g.T, g.T_err_prob, g.T_state, t)
+            cw += ok
+            cp += ok_p
+            if ok_p:
+                assert top_p == o["order"][t], "%s iteration %d" % (precision, t)
+        _log("%s cfg2: probable bound / worst case %.3e (median), max |dT|/prob-bound %.3e; certified %d "
+             "(probable) vs %d (worst case) of %d" % (
+                 precision, float(np.median(g.T_err_prob[fin] / np.maximum(g.T_err[fin], 1e-300))),
+                 float(np.max(dT / (g.T_err_prob[fin] + tol64))), cp, cw, p - 1))
+        assert cp >= cw
 
 
 def _gap_certified(T, E, state, t):
