@@ -38,9 +38,10 @@ typedef enum lingam_status {
   LINGAM_E_INVALID = 1,     /* bad argument: null pointer, n < 2, p < 1, size overflow,
                                wrong struct_size, forced order not a prefix of a permutation */
   LINGAM_E_NONFINITE = 2,   /* NaN or Inf in X (result.bad_i = variable) */
-  LINGAM_E_DEGENERATE = 3,  /* a row of zero variance (bad_i), or an evaluated pair with
-                               1 - corr^2 <= 1e-12 (bad_i, bad_j): the residual cannot be
-                               normalised */
+  LINGAM_E_DEGENERATE = 3,  /* a row of zero variance (bad_i), or a pair of remaining
+                               variables with 1 - corr^2 <= 1e-12 (bad_i, bad_j), checked for
+                               every pair at the start of each iteration, pruned or not: the
+                               residual cannot be normalised */
   LINGAM_E_NOMEM = 4,       /* device allocation failed or the caller's workspace is too small */
   LINGAM_E_DEVICE = 5,      /* HIP runtime error; lingam_last_error() holds the text */
   LINGAM_E_UNSUPPORTED = 6  /* option combination not supported */

@@ -802,6 +802,9 @@ lingam_status fit_single(const void* X, int64_t n, int64_t p, const lingam_opts&
 // layout (a caller's workspace, or a repeated allocation at the same
 // address); every graph is a chain of kernel nodes (the buffers are set by
 // fill kernels outside the windows, never by memset nodes).
+// The cache lives until the process ends and its graphs are not destroyed
+// at exit (the HIP runtime may already be torn down by then); it is
+// cleared whenever it reaches GRAPH_CACHE_MAX entries.
 struct GraphCache {
   std::mutex mu;
   std::unordered_map<uint64_t, hipGraphExec_t> execs;
@@ -816,7 +819,10 @@ uint64_t mix64(uint64_t h, uint64_t v) {
 
 uint64_t batch_layout_key(const char* base, uint64_t bytes, int32_t count, const lingam_dataset* sets,
                           const lingam_opts& o, int refresh_every, const Plan& pl) {
-  uint64_t h = mix64(0, reinterpret_cast<uintptr_t>(base));
+  // an instantiated graph belongs to the device it was captured on
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  uint64_t h = mix64((uint64_t)(uint32_t)dev, reinterpret_cast<uintptr_t>(base));
   h = mix64(h, bytes);
   h = mix64(h, (uint64_t)count);
   for (int k = 0; k < count; ++k) {
