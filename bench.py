@@ -50,7 +50,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("kernels.hip", "lingam_internal.h", "fp64_math.h")
+KERNEL_SOURCES = ("paper_2109_13993_amd/csrc/kernels.hip", "paper_2109_13993_amd/csrc/lingam_internal.h",
+                  "paper_2109_13993_amd/csrc/fp64_math.h", "include/lingam.h")
 
 
 def kernel_source_digest():
@@ -61,7 +62,7 @@ def kernel_source_digest():
     import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        text = open(os.path.join(ROOT, "paper_2109_13993_amd", "csrc", name)).read()
+        text = open(os.path.join(ROOT, name)).read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
         h.update(" ".join(text.split()).encode())

@@ -98,9 +98,16 @@ def flux(names=None, n=10000, precisions=("mixed",), reps=1):
         ds = synth.flux_like_dataset(p, n, np.random.default_rng([5, 6, p]))
         X = torch.from_numpy(ds.X).to("cuda:0")
         for prec in precisions:
-            t, r = _timed(lambda: lg.fit_order(X, precision=prec, want_T=False, want_H=False), reps)
-            _emit({"experiment": "flux", "stand_in_for": name, "p": p, "n": n, "precision": prec,
-                   "seconds": t, "pairs_evaluated": r.pairs_evaluated})
+            rec = {"experiment": "flux", "stand_in_for": name, "p": p, "n": n, "precision": prec}
+            try:
+                t, r = _timed(lambda: lg.fit_order(X, precision=prec, want_T=False, want_H=False), reps)
+                unpruned = (p + 1) * p * (p - 1) // 6
+                rec.update(status="ok", seconds=t, pairs_evaluated=r.pairs_evaluated,
+                           evaluated_share_of_unpruned=r.pairs_evaluated / unpruned)
+            except lg.LingamError as e:
+                # near-collinear stand-ins can hold pairs with 1 - corr^2 <= 1e-12
+                rec.update(status="degenerate" if e.status == lg.E_DEGENERATE else str(e.status), error=str(e))
+            _emit(rec)
     # exactly collinear: the search must stop with DEGENERATE
     ds = synth.flux_like_dataset(85, 2000, np.random.default_rng([5, 7]), noise=0.0)
     try:
