@@ -143,7 +143,14 @@ def uneven_datasets(count: int = 64, rng=None, p_range=(20, 200), n_range=(1000,
 def paper_scalability_dataset(p: int, n: int, dense: bool, rng) -> Dataset:
     """The scalability workload of Sec. 5.4: parents per variable U[1, 0.2p]
     (sparse) or U[0.25p, 0.5p] (dense), weights +-U[0.5, 0.95], noise
-    sign(g)|g|^e with e ~ U([0.5, 0.8] u [1.2, 2]), rows permuted."""
+    sign(g)|g|^e with e ~ U([0.5, 0.8] u [1.2, 2]), rows permuted.
+
+    The paper does not say how the variables are scaled.  Summed over up to
+    0.5p parents with weights near 1, the variances would grow geometrically
+    along the order until the deep variables are exact linear functions of
+    their parents in binary64; so each variable is scaled to unit sample
+    variance once it is generated, before its children are formed (its row
+    of B and its noise are scaled with it, so X = B X + N still holds)."""
     lo, hi = (1, max(1, int(0.2 * p))) if not dense else (max(1, int(0.25 * p)), max(1, int(0.5 * p)))
     B_gen = np.zeros((p, p))
     for i in range(1, p):
@@ -155,7 +162,12 @@ def paper_scalability_dataset(p: int, n: int, dense: bool, rng) -> Dataset:
         e = rng.uniform(0.5, 0.8) if rng.random() < 0.5 else rng.uniform(1.2, 2.0)
         g = rng.standard_normal(n)
         E[i] = np.sign(g) * np.abs(g) ** e
-    X_gen = _forward(B_gen, E)
+    X_gen = np.empty((p, n))
+    for i in range(p):
+        row = E[i] + B_gen[i, :i] @ X_gen[:i] if i > 0 else E[i].copy()
+        s = row.std(ddof=1)
+        X_gen[i] = row / s
+        B_gen[i] /= s
     perm = rng.permutation(p)
     inv = np.empty(p, dtype=np.int64)
     inv[perm] = np.arange(p)
