@@ -12,7 +12,7 @@ Parameters (lingam_opts fields):
   batch_queue    batches: device work queue (1) or one grid slice per set (0)
   graph          batches: HIP-graph windows replayed from a workspace (1)
 
-A tuned entry is keyed by the device (name, ISA, HIP version) and a bucket
+A tuned entry is keyed by the device (ISA and compute-unit count) and a bucket
 of the problem: kind (single / batch), precision, and p and n rounded up to
 powers of two.  Entries live in a JSON cache ($LINGAM_TUNE_CACHE, default
 ~/.cache/lingam_mi355x/tune.json); entries shipped with the package
@@ -53,13 +53,14 @@ _tables = None
 
 
 def device_key() -> str:
-    """Name, ISA and HIP version of device 0."""
+    """ISA and compute-unit count of device 0 (the marketing name is left
+    out: it depends on the host's device-id tables)."""
     global _device_key
     if _device_key is None:
         import torch
         props = torch.cuda.get_device_properties(0)
         arch = getattr(props, "gcnArchName", "unknown").split(":")[0]
-        _device_key = "%s|%s|hip %s" % (props.name, arch, torch.version.hip)
+        _device_key = "%s|%d CUs" % (arch, props.multi_processor_count)
     return _device_key
 
 
