@@ -331,29 +331,12 @@ Dev carve_set(Arena& al, int64_t n, int64_t p, const Plan& pl, const lingam_opts
   return d;
 }
 
-// Initial contents of one data set's buffers (queued on s; fills by kernel,
-// no memset nodes).
-void init_set(const Dev& d, const lingam_opts& o, int limit, hipStream_t s, std::vector<int32_t>& iota) {
-  const size_t P = (size_t)d.p, pp = P * P;
+// The forced prefix of the order (host memory of the caller) to the device;
+// every other initial value is set by launch_init_sets.
+void upload_forced(const Dev& d, const lingam_opts& o, hipStream_t s) {
   if (o.forced_len > 0)
     HIPCHK(hipMemcpyAsync(const_cast<int32_t*>(d.forced), o.forced_order, sizeof(int32_t) * o.forced_len,
                           hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(d.idx[0], iota.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(d.ord[0], iota.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
-  // zero padding past n in the second row buffer (the first is written whole by the normalisation)
-  HIPCHK(launch_fill_u8(static_cast<uint8_t*>(d.Z[1]),
-                        (int64_t)(P * d.ldz * (d.store32 ? sizeof(float) : sizeof(double))), 0, s));
-  HIPCHK(launch_fill(d.M, (int64_t)pp, NAN, s));
-  HIPCHK(launch_fill_u8(d.pend, (int64_t)pp, 0, s));
-  HIPCHK(launch_fill(d.Tall, (int64_t)pp, NAN, s));
-  HIPCHK(launch_fill_u8(d.Tstate, (int64_t)pp, 0, s));
-  HIPCHK(launch_fill(d.Hall, (int64_t)pp, NAN, s));
-  HIPCHK(launch_fill(d.Terr, (int64_t)pp, NAN, s));
-  HIPCHK(launch_fill(d.Terrp, (int64_t)pp, NAN, s));
-  if (d.Mrec) HIPCHK(launch_fill(d.Mrec, (int64_t)d.rec * (int64_t)pp, NAN, s));
-  HIPCHK(launch_fill_u8(reinterpret_cast<uint8_t*>(d.order), (int64_t)(4 * P), 0xff, s));
-  HIPCHK(launch_fill_u8(reinterpret_cast<uint8_t*>(d.pair_slots), (int64_t)(2 * PAIR_SLOTS * 8), 0, s));
-  (void)limit;
 }
 
 // Launch sequence of a batch (a single search is a batch of one).
@@ -475,13 +458,17 @@ struct Fit {
   }
 };
 
-void copy_results(const Dev& d, const Ctl& c, int64_t n, lingam_result* out, hipStream_t s) {
+// The results of one data set in two steps, so that a batch waits once for
+// all of its sets: queue the device-to-host copies (after launch_sum_slots),
+// then, after the stream is synchronised, fill in the rest.
+struct ResultCopy {
+  unsigned long long slots[2];
+};
+
+void queue_results(const Dev& d, lingam_result* out, ResultCopy* rc, hipStream_t s) {
   const size_t P = (size_t)d.p, pp = P * P;
-  std::vector<int32_t> order(P);
-  std::vector<unsigned long long> slots(2 * PAIR_SLOTS);
-  HIPCHK(hipMemcpyAsync(order.data(), d.order, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(slots.data(), d.pair_slots, sizeof(unsigned long long) * 2 * PAIR_SLOTS,
-                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(out->order, d.order, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(rc->slots, d.pair_slots, sizeof(rc->slots), hipMemcpyDeviceToHost, s));
   if (out->T) HIPCHK(hipMemcpyAsync(out->T, d.Tall, sizeof(double) * pp, hipMemcpyDeviceToHost, s));
   if (out->T_state) HIPCHK(hipMemcpyAsync(out->T_state, d.Tstate, pp, hipMemcpyDeviceToHost, s));
   if (out->H) HIPCHK(hipMemcpyAsync(out->H, d.Hall, sizeof(double) * pp, hipMemcpyDeviceToHost, s));
@@ -491,20 +478,17 @@ void copy_results(const Dev& d, const Ctl& c, int64_t n, lingam_result* out, hip
     HIPCHK(hipMemcpyAsync(out->T_err_prob, d.Terrp, sizeof(double) * pp, hipMemcpyDeviceToHost, s));
   if (out->M && d.rec > 0)
     HIPCHK(hipMemcpyAsync(out->M, d.Mrec, sizeof(double) * pp * d.rec, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  std::memcpy(out->order, order.data(), sizeof(int32_t) * P);
-  uint64_t ev = 0, comp = 0;
-  for (int k = 0; k < PAIR_SLOTS; ++k) {
-    ev += slots[(size_t)k];
-    comp += slots[(size_t)(PAIR_SLOTS + k)];
-  }
-  out->pairs_evaluated = ev;
-  out->pair_samples = ev * (uint64_t)n;
-  out->pairs_computed = comp;
+}
+
+void finish_results(const Dev& d, const Ctl& c, int64_t n, const ResultCopy& rc, lingam_result* out) {
+  const size_t P = (size_t)d.p;
+  out->pairs_evaluated = rc.slots[0];
+  out->pair_samples = rc.slots[0] * (uint64_t)n;
+  out->pairs_computed = rc.slots[1];
   out->threshold_rounds = c.rounds_total;
   out->bands = c.bands_total;
   int it = 0;
-  for (size_t k = 0; k < P; ++k) if (order[k] >= 0) ++it;
+  for (size_t k = 0; k < P; ++k) if (out->order[k] >= 0) ++it;
   out->iterations = it;
   if (c.status != ST_OK) {
     out->bad_i = c.bad_i;
@@ -512,6 +496,14 @@ void copy_results(const Dev& d, const Ctl& c, int64_t n, lingam_result* out, hip
     out->status = c.status == ST_NONFINITE ? LINGAM_E_NONFINITE
                 : c.status == ST_DEGENERATE ? LINGAM_E_DEGENERATE : LINGAM_E_INVALID;
   }
+}
+
+void copy_results(const Batch& b, const Dev& d, const Ctl& c, int64_t n, lingam_result* out, hipStream_t s) {
+  ResultCopy rc{};
+  HIPCHK(launch_sum_slots(b, s));
+  queue_results(d, out, &rc, s);
+  HIPCHK(hipStreamSynchronize(s));
+  finish_results(d, c, n, rc, out);
 }
 
 lingam_status status_from(const HipFail& e) {
@@ -721,17 +713,9 @@ lingam_status fit_single(const void* X, int64_t n, int64_t p, const lingam_opts&
     } else {
       d.X = X;
     }
+    // (L.d stays alive for the whole call, so the copy needs no wait)
     HIPCHK(hipMemcpyAsync(L.dd, &d, sizeof(Dev), hipMemcpyHostToDevice, f.s));
-    std::vector<int32_t> iota((size_t)p);
-    for (int64_t k = 0; k < p; ++k) iota[(size_t)k] = (int32_t)k;
-    init_set(d, o, limit, f.s, iota);
-    Ctl c0;
-    std::memset(&c0, 0, sizeof(c0));
-    c0.halt_iter = -1;
-    c0.root = -1;
-    c0.bad_i = c0.bad_j = -1;
-    HIPCHK(hipMemcpyAsync(L.ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, f.s));
-    HIPCHK(hipStreamSynchronize(f.s));  // host temporaries (d, iota, c0) are no longer needed
+    upload_forced(d, o, f.s);
 
     f.b.dd = L.dd;
     f.b.count = 1;
@@ -743,6 +727,7 @@ lingam_status fit_single(const void* X, int64_t n, int64_t p, const lingam_opts&
     f.b.mixed = mixed ? 1 : 0;
     f.b.store32 = o.precision == LINGAM_PREC_FP32_STORAGE ? 1 : 0;
     f.b.queue = o.batch_queue ? 1 : 0;
+    HIPCHK(launch_init_sets(f.b, f.s));
 
     if (events) {
       HIPCHK(hipEventCreate(&ev0));
@@ -768,7 +753,7 @@ lingam_status fit_single(const void* X, int64_t n, int64_t p, const lingam_opts&
         HIPCHK(hipMemcpyAsync(out->B, d.Bout, sizeof(double) * p * p, hipMemcpyDeviceToHost, f.s));
     }
     if (events) HIPCHK(hipEventRecord(ev1, f.s));
-    copy_results(d, c, n, out, f.s);
+    copy_results(f.b, d, c, n, out, f.s);
     float ms = 0.f;
     if (events && hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) out->seconds_device = ms * 1e-3;
     if (timer.on) {
@@ -1115,8 +1100,6 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
     }
     f.ps.resize((size_t)count);
     f.limits.resize((size_t)count);
-    std::vector<int32_t> iota((size_t)p_max);
-    for (int64_t k = 0; k < p_max; ++k) iota[(size_t)k] = (int32_t)k;
     int nchunk_max = 1;
     for (int k = 0; k < count; ++k) {
       const lingam_dataset& ds = sets[k];
@@ -1135,7 +1118,6 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
       } else if (L.xb[(size_t)k]) {
         HIPCHK(hipMemcpyAsync(L.xb[(size_t)k], ds.X, x_bytes(nk, pk, o), hipMemcpyHostToDevice, f.s));
       }
-      init_set(d, o, limit, f.s, iota);
       f.ps[(size_t)k] = pk;
       f.limits[(size_t)k] = limit;
       nchunk_max = std::max(nchunk_max, d.nchunk);
@@ -1144,15 +1126,6 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
     Dev* dd = L.dd;
     std::vector<Dev>& devs = L.devs;
     HIPCHK(hipMemcpyAsync(dd, devs.data(), sizeof(Dev) * count, hipMemcpyHostToDevice, f.s));
-    std::vector<Ctl> c0((size_t)count);
-    std::memset(c0.data(), 0, sizeof(Ctl) * count);
-    for (auto& c : c0) {
-      c.halt_iter = -1;
-      c.root = -1;
-      c.bad_i = c.bad_j = -1;
-    }
-    HIPCHK(hipMemcpyAsync(ctls, c0.data(), sizeof(Ctl) * count, hipMemcpyHostToDevice, f.s));
-    HIPCHK(hipStreamSynchronize(f.s));
 
     // the work queue's list of sets, latest-ending first: the sets with an
     // iteration at t are a prefix of it
@@ -1177,6 +1150,7 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
     f.b.queue = o.batch_queue ? 1 : 0;
     int limit_max = 0;
     for (int l : f.limits) limit_max = std::max(limit_max, l);
+    HIPCHK(launch_init_sets(f.b, f.s));
 
     HIPCHK(hipEventCreate(&ev0));
     HIPCHK(hipEventCreate(&ev1));
@@ -1215,13 +1189,17 @@ lingam_status lingam_fit_order_batch(int32_t count, const lingam_dataset* sets, 
       if (c.status == ST_OK) g.drive_one(ctls + k, tf + 1, f.limits[(size_t)k], (int)sets[k].p);
     }
     HIPCHK(hipEventRecord(ev1, f.s));
+    // every set's results in one wait
+    HIPCHK(launch_sum_slots(f.b, f.s));
     HIPCHK(hipMemcpyAsync(cs.data(), ctls, sizeof(Ctl) * count, hipMemcpyDeviceToHost, f.s));
+    std::vector<ResultCopy> rcs((size_t)count);
+    for (int k = 0; k < count; ++k) queue_results(devs[(size_t)k], &outs[k], &rcs[(size_t)k], f.s);
     HIPCHK(hipStreamSynchronize(f.s));
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ev0, ev1);
     st = LINGAM_OK;
     for (int k = 0; k < count; ++k) {
-      copy_results(devs[(size_t)k], cs[(size_t)k], devs[(size_t)k].n, &outs[k], f.s);
+      finish_results(devs[(size_t)k], cs[(size_t)k], devs[(size_t)k].n, rcs[(size_t)k], &outs[k]);
       outs[k].seconds_device = ms * 1e-3;
       if (timer.on) {
         outs[k].seconds_pair_kernel = timer.total_seconds();

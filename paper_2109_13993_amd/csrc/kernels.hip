@@ -1647,6 +1647,103 @@ hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_m
   return hipGetLastError();
 }
 
+// ============================================================================
+// initial contents of a search's buffers (one launch for every data set)
+// ============================================================================
+// Tests, records and results "not evaluated" (NaN) or empty, the positions
+// and original-index ranks the identity, the pair counters zero, the zero
+// padding past n of the second row buffer (the Gram sums over whole
+// 64-sample stages), and the control block.
+template <typename S>
+__device__ __forceinline__ void init_set_body(const Dev& d) {
+  const int64_t P = d.p, pp = P * P;
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, step = (int64_t)gridDim.x * blockDim.x;
+  const double nan = __builtin_nan("");
+  for (int64_t e = g; e < pp; e += step) {
+    d.M[e] = nan;
+    d.Tall[e] = nan;
+    d.Hall[e] = nan;
+    d.Terr[e] = nan;
+    d.Terrp[e] = nan;
+    d.Tstate[e] = 0;
+    d.pend[e] = 0;
+  }
+  if (d.Mrec)
+    for (int64_t e = g; e < (int64_t)d.rec * pp; e += step) d.Mrec[e] = nan;
+  for (int64_t i = g; i < P; i += step) {
+    d.idx[0][i] = (int32_t)i;
+    d.ord[0][i] = (int32_t)i;
+    d.order[i] = -1;
+  }
+  for (int64_t e = g; e < 2 * PAIR_SLOTS; e += step) d.pair_slots[e] = 0ull;
+  const int64_t pad = d.ldz - d.n;
+  S* z1 = static_cast<S*>(d.Z[1]);
+  for (int64_t e = g; e < P * pad; e += step) z1[(e / pad) * d.ldz + d.n + e % pad] = (S)0;
+  if (g == 0) {
+    Ctl c{};
+    c.halt_iter = -1;
+    c.root = -1;
+    c.bad_i = c.bad_j = -1;
+    *d.ctl = c;
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_init_set(const Dev* __restrict__ devs, const Dev one) {
+  if (devs)
+    init_set_body<S>(devs[blockIdx.z]);
+  else
+    init_set_body<S>(one);
+}
+
+hipError_t launch_init_sets(const Batch& b, hipStream_t s) {
+  const int64_t P = b.p_max;
+  const int64_t work = std::max<int64_t>(P * P, P * 256);
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024 / std::min(b.count, 16), (work + 255) / 256));
+  if (b.store32)
+    hipLaunchKernelGGL(k_init_set<float>, dim3(blocks, 1, b.count), dim3(256), 0, s, DEVS(b));
+  else
+    hipLaunchKernelGGL(k_init_set<double>, dim3(blocks, 1, b.count), dim3(256), 0, s, DEVS(b));
+  return hipGetLastError();
+}
+
+// Sum the spread pair counters of every data set into slots 0 (evaluated)
+// and 1 (computed), for the host to read with its results.
+__device__ __forceinline__ void sum_slots_body(const Dev& d) {
+  __shared__ unsigned long long sh[2][4];
+  unsigned long long ev = 0ull, comp = 0ull;
+  for (int k = threadIdx.x; k < PAIR_SLOTS; k += 256) {
+    ev += d.pair_slots[k];
+    comp += d.pair_slots[PAIR_SLOTS + k];
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    ev += __shfl_xor(ev, m, 64);
+    comp += __shfl_xor(comp, m, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = ev;
+    sh[1][threadIdx.x >> 6] = comp;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    d.pair_slots[0] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+    d.pair_slots[1] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sum_slots(const Dev* __restrict__ devs, const Dev one) {
+  if (devs)
+    sum_slots_body(devs[blockIdx.z]);
+  else
+    sum_slots_body(one);
+}
+
+hipError_t launch_sum_slots(const Batch& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_slots, dim3(1, 1, b.count), dim3(256), 0, s, DEVS(b));
+  return hipGetLastError();
+}
+
 __global__ void k_window_reset(const Dev* __restrict__ devs, const Dev one) {
   Ctl* ctl = devs ? devs[blockIdx.z].ctl : one.ctl;
   ctl->win_bands = 0;

@@ -238,6 +238,12 @@ hipError_t launch_resume(const Batch& b, hipStream_t s);
 hipError_t launch_gather(const double* X, int64_t n_src, int64_t p, const int64_t* idx, int64_t n_idx,
                          double* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
+// Initial contents of every data set's buffers and control block (after the
+// descriptors are on the device; before the first kernel of the search).
+hipError_t launch_init_sets(const Batch& b, hipStream_t s);
+// The pair counters of every data set summed into pair_slots[0] (pairs
+// evaluated) and [1] (computed), after the search.
+hipError_t launch_sum_slots(const Batch& b, hipStream_t s);
 // Hardware binary32 exp2 / log2 against binary64 over every argument of the
 // ranges the mixed-precision terms use (errors in units of u32 = 2^-24):
 // [0] v_exp_f32 on [-126, 0] (relative), [1] v_log_f32 on [1, 2] (absolute).

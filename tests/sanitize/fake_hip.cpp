@@ -144,6 +144,45 @@ hipError_t launch_gather(const double* X, int64_t n_src, int64_t p, const int64_
     }
   return hipSuccess;
 }
+// initial contents and counter sums, as the device kernels set them
+static void init_one(const Dev& d) {
+  const int64_t P = d.p, pp = P * P;
+  const double nan = __builtin_nan("");
+  for (int64_t e = 0; e < pp; ++e) {
+    d.M[e] = d.Tall[e] = d.Hall[e] = d.Terr[e] = d.Terrp[e] = nan;
+    d.Tstate[e] = 0;
+    d.pend[e] = 0;
+  }
+  if (d.Mrec)
+    for (int64_t e = 0; e < (int64_t)d.rec * pp; ++e) d.Mrec[e] = nan;
+  for (int64_t i = 0; i < P; ++i) {
+    d.idx[0][i] = d.ord[0][i] = (int32_t)i;
+    d.order[i] = -1;
+  }
+  for (int e = 0; e < 2 * PAIR_SLOTS; ++e) d.pair_slots[e] = 0;
+  Ctl c{};
+  c.halt_iter = -1;
+  c.root = -1;
+  c.bad_i = c.bad_j = -1;
+  *d.ctl = c;
+}
+hipError_t launch_init_sets(const Batch& b, hipStream_t) {
+  for (int k = 0; k < b.count; ++k) init_one(b.count == 1 ? b.one : b.dd[k]);
+  return hipSuccess;
+}
+hipError_t launch_sum_slots(const Batch& b, hipStream_t) {
+  for (int k = 0; k < b.count; ++k) {
+    const Dev& d = b.count == 1 ? b.one : b.dd[k];
+    unsigned long long ev = 0, comp = 0;
+    for (int i = 0; i < PAIR_SLOTS; ++i) {
+      ev += d.pair_slots[i];
+      comp += d.pair_slots[PAIR_SLOTS + i];
+    }
+    d.pair_slots[0] = ev;
+    d.pair_slots[1] = comp;
+  }
+  return hipSuccess;
+}
 hipError_t launch_standardize(const Batch&, hipStream_t) { return hipSuccess; }
 hipError_t launch_gram(const Batch&, int, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_iter_start(const Batch&, int, double, double, int, int, hipStream_t) { return hipSuccess; }
