@@ -1371,15 +1371,30 @@ __device__ __forceinline__ int band_row(const Dev& d, const BandRows& br, int qr
   return (y < br.t_lo || y >= br.t_hi) ? y : -1;
 }
 
-// Row x of the band, by one work-group of 256 threads: the pending tests
-// from the chunk partial sums, then the row's score S_x recomputed over all
-// its tests in ascending original index of the other variable (so its bits
-// do not depend on positions), its rounding bound and its complete flag.
+// Row x of the band: the pending tests from the chunk partial sums, then
+// the row's score S_x recomputed over all its tests in ascending original
+// index of the other variable (so its bits do not depend on positions), its
+// rounding bound and its complete flag.
 // In the mixed modes it also forms the rounding bound eps of every new test
 // (the sum of the bounds of its four entropies) and the bound of the row's
 // score: a test moved by at most eps changes min(0, M)^2 by at most
 // 2 |min(0, M)| eps + 3 eps^2, and not at all when M >= eps.
+//
+// W = 256: the whole work-group scores the row; thread v takes the tests at
+// v, v + 256, ... and the four wave sums are added pairwise.  W = 64: one
+// wave scores the row and each lane keeps the four partial sums that
+// threads lane, lane + 64, lane + 128 and lane + 192 of the work-group form,
+// reduced in the same order, so both forms give the same bits.  The wave
+// form scores four rows of a work-group at once with no barrier; short rows
+// use it.
+struct RowAcc {
+  double s = 0.0, es = 0.0, esp = 0.0;
+};
+
+template <int W>
 __device__ __forceinline__ void score_row(const Dev& d, int t, int x) {
+  static_assert(W == 64 || W == 256, "a row is scored by one wave or by the work-group");
+  constexpr int K = 256 / W;  // partial sums per thread
   const int r = rows_left(d, t), p = d.p;
   const int buf = t & 1;
   double* __restrict__ M = d.M;
@@ -1395,18 +1410,14 @@ __device__ __forceinline__ void score_row(const Dev& d, int t, int x) {
   double* __restrict__ Mepsp = d.Mepsp;
   const double* __restrict__ eH = d.eH;
   const double* __restrict__ eHp = d.eHp;
-  __shared__ double sh[4];
-  __shared__ int shi[4];
-  double s = 0.0, es = 0.0, esp = 0.0;
-  int incomplete = 0;
   const double hx = H[x];
   const double* sig = d.Sig[buf] + (int64_t)x * p;
   const double dx = dsc[x];
-  for (int q = threadIdx.x; q < r; q += 256) {
-    const int w = ord[q];
-    if (w == x) continue;
-    // the flag, the stored test and its bound are fetched together; only a
-    // pending test needs a second, dependent fetch (its chunk partials)
+  int incomplete = 0;
+  // test (x, w): a pending one is formed from its chunk partials (a second,
+  // dependent fetch after the flag, the stored test and its bound), then it
+  // is added to the row's score and bounds
+  auto score_test = [&](int w, RowAcc& acc) {
     const int64_t o = (int64_t)x * p + w;
     const uint8_t pd = pend[o];
     double mv = M[o], ev = mixed ? Meps[o] : 0.0, evp = mixed ? Mepsp[o] : 0.0;
@@ -1439,18 +1450,38 @@ __device__ __forceinline__ void score_row(const Dev& d, int t, int x) {
       incomplete = 1;
     } else {
       const double neg = mv < 0.0 ? mv : 0.0;
-      s += neg * neg;
-      if (mv < ev) es += 2.0 * (-neg) * ev + 3.0 * ev * ev;
-      if (mv < evp) esp += 2.0 * (-neg) * evp + 3.0 * evp * evp;
+      acc.s += neg * neg;
+      if (mv < ev) acc.es += 2.0 * (-neg) * ev + 3.0 * ev * ev;
+      if (mv < evp) acc.esp += 2.0 * (-neg) * evp + 3.0 * evp * evp;
     }
+  };
+  const int v0 = W == 256 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+  RowAcc acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    for (int q = v0 + 64 * k; q < r; q += 256) {
+      const int w = ord[q];
+      if (w != x) score_test(w, acc[k]);
+    }
+  double s, es = 0.0, esp = 0.0;
+  if constexpr (W == 256) {
+    __shared__ double sh[4];
+    __shared__ int shi[4];
+    s = block_sum256(acc[0].s, sh);
+    if (mixed) {
+      es = block_sum256(acc[0].es, sh);
+      esp = block_sum256(acc[0].esp, sh);
+    }
+    incomplete = block_or256(incomplete, shi);
+  } else {
+    s = (wave_sum(acc[0].s) + wave_sum(acc[1].s)) + (wave_sum(acc[2].s) + wave_sum(acc[3].s));
+    if (mixed) {
+      es = (wave_sum(acc[0].es) + wave_sum(acc[1].es)) + (wave_sum(acc[2].es) + wave_sum(acc[3].es));
+      esp = (wave_sum(acc[0].esp) + wave_sum(acc[1].esp)) + (wave_sum(acc[2].esp) + wave_sum(acc[3].esp));
+    }
+    incomplete = __any(incomplete) ? 1 : 0;
   }
-  s = block_sum256(s, sh);
-  if (mixed) {
-    es = block_sum256(es, sh);
-    esp = block_sum256(esp, sh);
-  }
-  incomplete = block_or256(incomplete, shi);
-  if (threadIdx.x == 0) {
+  if (v0 == 0) {
     d.S[x] = s;
     d.eT[x] = es;
     d.eTp[x] = esp;
@@ -1534,11 +1565,22 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a, do
   __syncthreads();
   if (s_stop) return;
   const BandRows br = s_br;
-  for (int qrow = blockIdx.x; qrow < br.rows; qrow += gridDim.x) {
-    const int x = band_row(d, br, qrow);
-    if (x < 0) continue;  // uniform over the work-group
-    score_row(d, t, x);
-    if (threadIdx.x == 0) s_wrote = 1;
+  if (r <= a.score_wave_rows) {
+    // one row per wave, four per work-group
+    const int wv = threadIdx.x >> 6;
+    for (int qrow = blockIdx.x * 4 + wv; qrow < br.rows; qrow += gridDim.x * 4) {
+      const int x = band_row(d, br, qrow);
+      if (x < 0) continue;  // uniform over the wave
+      score_row<64>(d, t, x);
+      if ((threadIdx.x & 63) == 0) s_wrote = 1;
+    }
+  } else {
+    for (int qrow = blockIdx.x; qrow < br.rows; qrow += gridDim.x) {
+      const int x = band_row(d, br, qrow);
+      if (x < 0) continue;  // uniform over the work-group
+      score_row<256>(d, t, x);
+      if (threadIdx.x == 0) s_wrote = 1;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1577,10 +1619,12 @@ __device__ __forceinline__ void k_score_queue_body(const Dev* __restrict__ devs,
     }
     fresh = false;
     const Dev& d = devs[act[pos]];
+    // short rows are claimed four at a time, one per wave
+    const int claim = rows_left(d, t) <= a.score_wave_rows ? 4 : 1;
     if (threadIdx.x == 0) {
       // a claim below the row count holds the set's band open (its decision
       // waits for this row), so its band fields read after it are stable
-      s_q = has_rows(act[pos]) ? (int)atomicAdd(&d.ctl->q_rows, 1u) : 0x7fffffff;
+      s_q = has_rows(act[pos]) ? (int)atomicAdd(&d.ctl->q_rows, (unsigned)claim) : 0x7fffffff;
       s_br = band_rows(d, t);
     }
     __syncthreads();
@@ -1589,13 +1633,20 @@ __device__ __forceinline__ void k_score_queue_body(const Dev* __restrict__ devs,
     __syncthreads();
     if (qrow >= br.rows) continue;
     fresh = true;
-    const int x = band_row(d, br, qrow);
-    if (x >= 0) score_row(d, t, x);
+    if (claim == 4) {
+      const int q = qrow + (int)(threadIdx.x >> 6);
+      const int x = q < br.rows ? band_row(d, br, q) : -1;
+      if (x >= 0) score_row<64>(d, t, x);
+    } else {
+      const int x = band_row(d, br, qrow);
+      if (x >= 0) score_row<256>(d, t, x);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence();
-      const unsigned prev = atomicAdd(&d.ctl->arrivals, 1u);
-      s_last = prev == (unsigned)br.rows - 1 ? 1 : 0;
+      const unsigned got = (unsigned)min(claim, br.rows - qrow);
+      const unsigned prev = atomicAdd(&d.ctl->arrivals, got);
+      s_last = prev + got == (unsigned)br.rows ? 1 : 0;
     }
     __syncthreads();
     if (s_last) {
@@ -1619,10 +1670,16 @@ __global__ __launch_bounds__(256) void k_score_queue(const Dev* __restrict__ dev
   k_score_queue_body(devs, act, nact, t, a, gamma_mult);
 }
 
-hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_mult, int dense, int ntb_hint,
+hipError_t launch_score(const Batch& b, int t, const BandArgs& band, double gamma_mult, int dense, int ntb_hint,
                         hipStream_t s) {
   const int r = b.p_max - t;
   if (r < 2) return hipSuccess;
+  // A batch has many more rows than a launch has work-groups, so one wave
+  // per row (four rows per group at once) keeps more rows in flight; one
+  // search has few rows per group and scores each with the whole group,
+  // which halves a row's latency.  Both forms give the same bits.
+  BandArgs a = band;
+  a.score_wave_rows = b.count > 1 ? 1 << 30 : 0;
   const int nb = (r + TB - 1) / TB;
   // rows when every variable is alive; after the first band of an iteration
   // few are, and a smaller grid keeps idle groups from filling the launch
@@ -1641,9 +1698,15 @@ hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_m
                        (const Dev*)b.dd, b.act, nact, t, a, gamma_mult);
     return hipGetLastError();
   }
+  // rows scored one per wave go four to a work-group
   const int rows = std::min(r, std::max(1, std::min(ntb_hint, nb)) * TB) + r;
-  const int cap = std::max(8, (dense ? 512 : 256) / std::min(b.count, 16));
-  hipLaunchKernelGGL(k_score, dim3(std::min(rows, cap), 1, b.count), dim3(256), 0, s, DEVS(b), t, a, gamma_mult);
+  const int groups = r <= a.score_wave_rows ? (rows + 3) / 4 : rows;
+  // every group of a set publishes its scores to the set's decision with a
+  // device-wide fence, whose cost grows with the number of groups: a large
+  // batch keeps about 1024 groups in all
+  const int cap = b.count == 1 ? (dense ? 512 : 256)
+                               : std::max(4, std::min((dense ? 512 : 256) / std::min(b.count, 16), 1024 / b.count));
+  hipLaunchKernelGGL(k_score, dim3(std::min(groups, cap), 1, b.count), dim3(256), 0, s, DEVS(b), t, a, gamma_mult);
   return hipGetLastError();
 }
 

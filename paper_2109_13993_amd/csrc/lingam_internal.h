@@ -176,6 +176,7 @@ struct BandArgs {
   int rows_per_group;  // alive rows per pair-kernel work-group
   int groups;     // pair-kernel work-groups one data set's later bands run on
   double band_target;  // pair-samples a later band of round 0 aims at
+  int score_wave_rows = 0;  // score rows of at most this many variables one per wave (else per work-group)
 };
 
 // What a launch covers: `count` data sets whose descriptors are at `dd` on
