@@ -531,7 +531,6 @@ __device__ __forceinline__ void iter_init_row(const Dev& d, int t, int x, double
     ctl->iter_bands = 0;
     ctl->arrivals = 0;
     ctl->q_next = 0;
-    ctl->q_rows = 0;
   }
 }
 
@@ -1044,15 +1043,11 @@ __device__ int find_set(const int32_t* __restrict__ act, int nact, int start, in
 
 template <bool MIXED, int RG, int TPW, int PS, typename S>
 __device__ __forceinline__ void k_pair_queue_body(const Dev* __restrict__ devs, const int32_t* __restrict__ act,
-                                                  int nact, int count, int t, BandArgs a) {
+                                                  int nact, int t, BandArgs a) {
   constexpr int NW = RG * (TB / TPW);
   __shared__ int s_best, s_i0, s_cnt, s_m, s_tb0, s_ntb;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int lane = threadIdx.x % 64;
-  // reopen every set's score rows for the score launch that follows (the
-  // previous score launch has ended, and the next starts after this one)
-  if (blockIdx.x == 0)
-    for (int k = threadIdx.x; k < count; k += blockDim.x) devs[k].ctl->q_rows = 0;
   if (nact < 1) return;
   int pos = (int)((int64_t)blockIdx.x * nact / gridDim.x);
   int cur_set = -1;
@@ -1120,8 +1115,8 @@ __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_band(const Dev* _
 template <bool MIXED, int RG, int TPW, int PS, typename S>
 __global__ __launch_bounds__(64 * RG * (TB / TPW)) void k_pair_queue(const Dev* __restrict__ devs,
                                                                     const int32_t* __restrict__ act, int nact,
-                                                                    int count, int t, BandArgs a) {
-  k_pair_queue_body<MIXED, RG, TPW, PS, S>(devs, act, nact, count, t, a);
+                                                                    int t, BandArgs a) {
+  k_pair_queue_body<MIXED, RG, TPW, PS, S>(devs, act, nact, t, a);
 }
 
 // Work-group shapes of the pair kernel (results do not depend on them;
@@ -1180,7 +1175,7 @@ static void launch_pair_shape(const Batch& b, int t, const BandArgs& a, int ntb_
     // the persistent grid: the work-groups the device holds at once
     const int gq = (resident_groups<MIXED, RG, TPW, PS, S>() + 7) / 8 * 8;
     hipExtLaunchKernelGGL((k_pair_queue<MIXED, RG, TPW, PS, S>), dim3(gq), blk, 0, s, ev0, ev1, 0,
-                          (const Dev*)b.dd, b.act, b.active_at(t), b.count, t, a);
+                          (const Dev*)b.dd, b.act, b.active_at(t), t, a);
   } else {
     hipExtLaunchKernelGGL((k_pair_band<MIXED, RG, TPW, PS, true, S>), g, blk, 0, s, ev0, ev1, 0,
                           (const Dev*)b.dd, b.one, t, a);
@@ -1332,19 +1327,6 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
     ctl->iter_bands += 1;
   }
 }
-
-// Rows whose tests can have changed in a band: the variables of the target
-// blocks, then the alive variables outside them.  One work-group per row
-// forms the pending tests from the chunk partial sums and recomputes the
-// row's score in a fixed order; the last group to finish then decides for
-// the iteration.
-// In the mixed mode it also forms the rounding bound eps of every new test
-// (the sum of the bounds of its four entropies) and the bound of the row's
-// score: a test moved by at most eps changes min(0, M)^2 by at most
-// 2 |min(0, M)| eps + 3 eps^2, and not at all when M >= eps.
-// Batch queue: a set's score rows are closed (no claim can succeed) from its
-// band decision until the next pair launch reopens them.
-constexpr uint32_t Q_CLOSED = 0x40000000u;
 
 // The rows whose tests can have changed in the current band: the variables
 // of the band's target blocks, then the alive variables outside them.  Row
@@ -1538,12 +1520,9 @@ __device__ __forceinline__ void band_decision(const Dev& d, int t, const BandArg
   }
   if (threadIdx.x == 0) {
     // ready for the next band: its pair launch starts claiming items at 0
-    // (no pair launch is running now); the score rows of this band stay
-    // closed for the rest of this launch and the next pair launch reopens
-    // them (batch queue)
+    // (no pair launch is running now)
     ctl->arrivals = 0;
     ctl->q_next = 0;
-    ctl->q_rows = Q_CLOSED;
   }
 }
 
@@ -1594,80 +1573,12 @@ __device__ __forceinline__ void k_score_body(const Dev& d, int t, BandArgs a, do
   band_decision(d, t, a, gamma_mult);
 }
 
-// A batch on the device work queue: work-groups claim rows of any data set
-// (Ctl::q_rows), first of the set they worked on last, and count each
-// finished row in (Ctl::arrivals, released after the row's scores); the
-// group that finishes a set's last row takes that set's decision.
-__device__ __forceinline__ void k_score_queue_body(const Dev* __restrict__ devs, const int32_t* __restrict__ act,
-                                                   int nact, int t, BandArgs a, double gamma_mult) {
-  __shared__ int s_best, s_q, s_last;
-  __shared__ BandRows s_br;
-  if (nact < 1) return;
-  auto has_rows = [&](int k) {
-    const Dev& d = devs[k];
-    const Ctl* c = d.ctl;
-    if (rows_left(d, t) < 2 || halted(c) || c->done) return false;
-    const int rows = (min(rows_left(d, t), (c->tb_next + c->ntb_next) * TB) - c->tb_next * TB) + c->n_alive;
-    return (int)__atomic_load_n(&c->q_rows, __ATOMIC_RELAXED) < rows;
-  };
-  int pos = (int)((int64_t)blockIdx.x * nact / gridDim.x);
-  bool fresh = true;
-  for (;;) {
-    if (!fresh) {
-      pos = find_set(act, nact, pos, &s_best, has_rows);
-      if (pos < 0) break;
-    }
-    fresh = false;
-    const Dev& d = devs[act[pos]];
-    // short rows are claimed four at a time, one per wave
-    const int claim = rows_left(d, t) <= a.score_wave_rows ? 4 : 1;
-    if (threadIdx.x == 0) {
-      // a claim below the row count holds the set's band open (its decision
-      // waits for this row), so its band fields read after it are stable
-      s_q = has_rows(act[pos]) ? (int)atomicAdd(&d.ctl->q_rows, (unsigned)claim) : 0x7fffffff;
-      s_br = band_rows(d, t);
-    }
-    __syncthreads();
-    const BandRows br = s_br;
-    const int qrow = s_q;
-    __syncthreads();
-    if (qrow >= br.rows) continue;
-    fresh = true;
-    if (claim == 4) {
-      const int q = qrow + (int)(threadIdx.x >> 6);
-      const int x = q < br.rows ? band_row(d, br, q) : -1;
-      if (x >= 0) score_row<64>(d, t, x);
-    } else {
-      const int x = band_row(d, br, qrow);
-      if (x >= 0) score_row<256>(d, t, x);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      const unsigned got = (unsigned)min(claim, br.rows - qrow);
-      const unsigned prev = atomicAdd(&d.ctl->arrivals, got);
-      s_last = prev + got == (unsigned)br.rows ? 1 : 0;
-    }
-    __syncthreads();
-    if (s_last) {
-      __threadfence();
-      band_decision(d, t, a, gamma_mult);
-      __syncthreads();
-    }
-  }
-}
-
 __global__ __launch_bounds__(256) void k_score(const Dev* __restrict__ devs, const Dev one, int t, BandArgs a,
                                                double gamma_mult) {
   if (devs)
     k_score_body(devs[blockIdx.z], t, a, gamma_mult);
   else
     k_score_body(one, t, a, gamma_mult);
-}
-
-__global__ __launch_bounds__(256) void k_score_queue(const Dev* __restrict__ devs, const int32_t* __restrict__ act,
-                                                     int nact, int t, BandArgs a, double gamma_mult) {
-  k_score_queue_body(devs, act, nact, t, a, gamma_mult);
 }
 
 hipError_t launch_score(const Batch& b, int t, const BandArgs& band, double gamma_mult, int dense, int ntb_hint,
@@ -1682,22 +1593,10 @@ hipError_t launch_score(const Batch& b, int t, const BandArgs& band, double gamm
   a.score_wave_rows = b.count > 1 ? 1 << 30 : 0;
   const int nb = (r + TB - 1) / TB;
   // rows when every variable is alive; after the first band of an iteration
-  // few are, and a smaller grid keeps idle groups from filling the launch
-  if (b.count > 1 && b.queue) {
-    // rows of every set on the device work queue, about 4 work-groups per CU
-    static int cus = 0;
-    if (cus == 0) {
-      int dev = 0;
-      if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
-                                                                    dev) != hipSuccess || cus < 1)
-        cus = 256;
-    }
-    const int nact = b.active_at(t);
-    const int rows_act = (std::min(r, std::max(1, std::min(ntb_hint, nb)) * TB) + r) * std::max(nact, 1);
-    hipLaunchKernelGGL(k_score_queue, dim3(std::max(8, std::min(4 * cus, rows_act))), dim3(256), 0, s,
-                       (const Dev*)b.dd, b.act, nact, t, a, gamma_mult);
-    return hipGetLastError();
-  }
+  // few are, and a smaller grid keeps idle groups from filling the launch.
+  // A batch scores in grid slices also when its pair items run on the work
+  // queue: a slice needs no claims, and a finished set's groups return at
+  // once (measured faster than claiming rows from a queue).
   // rows scored one per wave go four to a work-group
   const int rows = std::min(r, std::max(1, std::min(ntb_hint, nb)) * TB) + r;
   const int groups = r <= a.score_wave_rows ? (rows + 3) / 4 : rows;
@@ -2164,7 +2063,6 @@ __device__ __forceinline__ void k_resume_body(const Dev& d) {
     ctl->halt_iter = -1;
     ctl->arrivals = 0;
     ctl->q_next = 0;
-    ctl->q_rows = 0;
   }
 }
 

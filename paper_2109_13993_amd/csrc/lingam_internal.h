@@ -57,10 +57,8 @@ struct Ctl {
   int32_t status;       // Status of the first error
   int32_t bad_i, bad_j; // compacted positions (pair error) or original index (row error)
   int32_t round;        // threshold round of the current iteration
-  uint32_t arrivals;     // work-groups (one data set) or rows (batch queue) of the running score
-                         // launch that have finished
+  uint32_t arrivals;     // work-groups of the running score launch that have finished
   uint32_t q_next;       // batch queue: pair-kernel items of the band claimed so far
-  uint32_t q_rows;       // batch queue: score rows of the band claimed so far
   int32_t n_alive;        // entries of the alive list (variables with S <= gamma)
   int32_t tb_next;        // target blocks [tb_next, tb_next + ntb_next) of the next band
   int32_t ntb_next;
