@@ -3,7 +3,9 @@
 //
 // Written for this range only, from the series
 //   log(1 + f) = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...),  s = f / (2 + f),
-// arranged so that f itself is the leading term,
+// arranged so that f itself is the leading term (the arrangement
+// f - (f^2/2 - s (f^2/2 + R)) of the classic Sun fdlibm log and log1p; the
+// coefficients here are the plain series terms 2/(2k+1), not a minimax fit),
 // after the reduction 1 + y = m 2^e with m in [sqrt(1/2), sqrt(2)) and
 // e in {0, 1}, so |s| <= 0.1716 and s^2 <= 0.02944; the terms through s^19
 // leave a truncation below 2^-56 of the result.  The rounding error of the

@@ -1404,10 +1404,23 @@ __device__ __forceinline__ void score_row(const Dev& d, int t, int x) {
     const uint8_t pd = pend[o];
     double mv = M[o], ev = mixed ? Meps[o] : 0.0, evp = mixed ? Mepsp[o] : 0.0;
     if (pd) {
+      // the chunk partials in chunk order; eight chunks' loads are issued
+      // before their sums, so a test waits for one memory round trip per
+      // eight chunks (a chunk past the last re-reads the last and is not
+      // added)
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      for (int c = 0; c < nchunk; ++c) {
-        const double* q = P + (((int64_t)c * p + x) * p + w) * 4;
-        a0 += q[0]; a1 += q[1]; a2 += q[2]; a3 += q[3];
+      const double* q0 = P + ((int64_t)x * p + w) * 4;
+      const int64_t cstride = (int64_t)p * p * 4;
+      for (int c0 = 0; c0 < nchunk; c0 += 8) {
+        double4 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          v[k] = *reinterpret_cast<const double4*>(q0 + (int64_t)min(c0 + k, nchunk - 1) * cstride);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (c0 + k < nchunk) {
+            a0 += v[k].x; a1 += v[k].y; a2 += v[k].z; a3 += v[k].w;
+          }
       }
       const double h_rx = happ_from_sums(a0, a1, n);  // H(r_x^(w))
       const double h_rw = happ_from_sums(a2, a3, n);  // H(r_w^(x))
