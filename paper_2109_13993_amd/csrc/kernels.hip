@@ -1913,35 +1913,67 @@ __device__ __forceinline__ void k_update_rows_body(const Dev& d, int t, int want
   const S* zr = Z + (int64_t)root * ldz;
   const S* zw = Z + (int64_t)w * ldz;
   S* zo = Zn + (int64_t)wn * ldz;
-  const int64_t step = (int64_t)segs * 256;
+  // two adjacent samples per thread and step, moved with one vector load
+  // per row and one vector store (rows start 16-byte aligned, and a sample
+  // at n, read as the second of a pair, lies in the row's padding and is
+  // neither stored nor summed)
+  using V2 = typename std::conditional<sizeof(S) == 8, double2, float2>::type;
+  const int64_t step2 = (int64_t)segs * 512;
+  const int64_t k0 = 2 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
   // binary64 arithmetic in every mode; binary32 rows are rounded once, on the store
+  auto update2 = [&](int64_t k, double& z0, double& z1) {
+    const V2 vw = *reinterpret_cast<const V2*>(zw + k), vr = *reinterpret_cast<const V2*>(zr + k);
+    z0 = ((double)vw.x - b * (double)vr.x) * sc;   // the rows are stored normalised
+    z1 = ((double)vw.y - b * (double)vr.y) * sc;
+    if (k + 1 < n) {
+      V2 o;
+      o.x = (S)z0;
+      o.y = (S)z1;
+      *reinterpret_cast<V2*>(zo + k) = o;
+    } else {
+      zo[k] = (S)z0;
+    }
+  };
   if (!want_h) {
-#pragma unroll 4
-    for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += step)
-      zo[k] = (S)(((double)zw[k] - b * (double)zr[k]) * sc);   // the rows are stored normalised
+    for (int64_t k = k0; k < n; k += step2) {
+      double z0, z1;
+      update2(k, z0, z1);
+    }
     return;
   }
-  double lc = 0.0, g = 0.0;
-  int64_t k = blockIdx.x * 256 + threadIdx.x;
+  // The even and the odd sample of each pair have sums of their own: a lane
+  // then accumulates the samples it did when it took one at a time, in the
+  // same order (terms that cancel exactly in exact arithmetic, +-c, still
+  // cancel exactly; a fused multiply-add adding -c to a rounded +c would
+  // leave the product's rounding error)
+  double lc = 0.0, g = 0.0, lc1 = 0.0, g1 = 0.0;
+  int64_t k = k0;
   if constexpr (MIXED) {
     const float ca = -2.0f * LOG2E_F, cg = -0.5f * LOG2E_F;
     while (k < n) {
-      float flc = 0.f, fg = 0.f;
-      for (int c = 0; c < 32 && k < n; ++c, k += step) {
-        const double zk = ((double)zw[k] - b * (double)zr[k]) * sc;
-        zo[k] = (S)zk;
-        terms_mixed((float)zk, ca, cg, flc, fg);   // the value the row holds
+      // binary32 lane sums of at most 32 terms
+      float flc = 0.f, fg = 0.f, flc1 = 0.f, fg1 = 0.f;
+      for (int c = 0; c < 32 && k < n; ++c, k += step2) {
+        double z0, z1;
+        update2(k, z0, z1);
+        terms_mixed((float)z0, ca, cg, flc, fg);   // the value the row holds
+        if (k + 1 < n) terms_mixed((float)z1, ca, cg, flc1, fg1);
       }
       lc += (double)flc * LN2;
       g += (double)fg;
+      lc1 += (double)flc1 * LN2;
+      g1 += (double)fg1;
     }
   } else {
-    for (; k < n; k += step) {
-      const double zk = ((double)zw[k] - b * (double)zr[k]) * sc;
-      zo[k] = (S)zk;
-      terms_f64(zk, lc, g);
+    for (; k < n; k += step2) {
+      double z0, z1;
+      update2(k, z0, z1);
+      terms_f64(z0, lc, g);
+      if (k + 1 < n) terms_f64(z1, lc1, g1);
     }
   }
+  lc += lc1;
+  g += g1;
   __shared__ double sh[4];
   lc = block_sum256(lc, sh);
   g = block_sum256(g, sh);
