@@ -1,12 +1,15 @@
 """Autotuner of the search's launch parameters on the GPU it runs on.
 
 What it tunes never changes a result: the order and every complete score
-are the same for any value (the threshold's band schedule, the sample chunk
-of the pair kernel's work-groups, and for batches the device work queue and
-graph replay only move work around).  It only changes the time.
+are the same for any value (the threshold's band schedule, and for batches
+the device work queue and graph replay only move work around).  It only
+changes the time.  The sample chunk of the pair kernel's work-groups is not
+tuned: it groups the per-sample sums, so another chunk length rounds them
+differently, and every entry keeps the default of 2048 samples (a single
+call and a batch then give the same bits whichever entries apply).
 
 Parameters (lingam_opts fields):
-  chunk_samples  samples per pair-kernel work-group chunk (multiple of 256)
+  chunk_samples  samples per pair-kernel work-group chunk (fixed at 2048)
   first_band_blocks  target blocks of an iteration's first threshold band
   band_target    pair-samples a later band of round 0 aims at
   batch_queue    batches: device work queue (1) or one grid slice per set (0)
@@ -22,7 +25,10 @@ a parameter is passed explicitly (tune=False switches this off).
 
 Tuning is coordinate descent: one parameter at a time over its candidates,
 each timed as the median of `reps` calls on a seeded synthetic workload of
-the bucket's shape (device-resident input), keeping the fastest.
+the bucket's shape (device-resident input), keeping the fastest.  A
+candidate replaces the current best only when it is at least MIN_GAIN (1%)
+faster, so that timing noise between nearly equal settings does not move an
+entry.
 
     python -m paper_2109_13993_amd.autotune single --p 500 --n 20000 --precision mixed
     python -m paper_2109_13993_amd.autotune batch --precision mixed --workload bootstrap
@@ -41,10 +47,11 @@ SHIPPED = os.path.join(HERE, "tuned.json")
 CACHE = os.environ.get("LINGAM_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "lingam_mi355x", "tune.json"))
 
+CHUNK_SAMPLES = 2048
+MIN_GAIN = 0.01
 SINGLE_SPACE = {
-    "chunk_samples": {"fp64": [1024, 2048, 4096], "mixed": [1024, 2048], "fp32_storage": [1024, 2048]},
     "first_band_blocks": [1, 2, 4, 8],
-    "band_target": [1e7, 2e7, 4e7, 6e7, 1e8],
+    "band_target": [1e7, 2e7, 4e7, 6e7, 1e8, 2e8, 4e8],
 }
 BATCH_SPACE = dict(SINGLE_SPACE, batch_queue=[1, 0], graph=[0, 1])
 
@@ -140,7 +147,7 @@ def _descend(space, start, timer, log):
             trial = dict(best, **{name: v})
             t = timer(trial)
             log("  %s=%s: %.2f ms" % (name, v, t * 1e3))
-            if t < best_t:
+            if t < best_t * (1.0 - MIN_GAIN):
                 best, best_t = trial, t
     return best, best_t
 
@@ -155,7 +162,7 @@ def tune_single(p: int, n: int, precision: str = "mixed", reps: int = 3, log=pri
     ds = synth.lingam_dataset(p, n, q, "laplace", rng=np.random.default_rng([2109, p, n]))
     X = torch.from_numpy(ds.X).to("cuda:0")
     space = {k: (v[precision] if isinstance(v, dict) else v) for k, v in SINGLE_SPACE.items()}
-    start = {"chunk_samples": 2048, "first_band_blocks": 4 if precision != "fp64" else 1,
+    start = {"chunk_samples": CHUNK_SAMPLES, "first_band_blocks": 4 if precision != "fp64" else 1,
              "band_target": 6e7 if precision != "fp64" else 2e7}
 
     def timer(params):
@@ -189,9 +196,9 @@ def tune_batch(sets, precision: str = "mixed", reps: int = 3, log=print, path: s
     import paper_2109_13993_amd as lg
     p, n = batch_shape(sets)
     space = {k: (v[precision] if isinstance(v, dict) else v) for k, v in BATCH_SPACE.items()}
-    start = {"chunk_samples": 2048, "first_band_blocks": 1, "band_target": 2e7, "batch_queue": 1, "graph": 0}
-    # one workspace for every trial: the largest layout is the shortest chunk's
-    need = max(lg.batch_workspace_size(sets, precision, chunk_samples=c) for c in space["chunk_samples"])
+    start = {"chunk_samples": CHUNK_SAMPLES, "first_band_blocks": 1, "band_target": 2e7, "batch_queue": 1, "graph": 0}
+    # one workspace for every trial (the layout depends on the chunk only)
+    need = lg.batch_workspace_size(sets, precision, chunk_samples=CHUNK_SAMPLES)
     ws = torch.empty(need + 4096, dtype=torch.uint8, device="cuda:0")
 
     def timer(params):
