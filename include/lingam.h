@@ -117,16 +117,18 @@ typedef struct lingam_opts {
   int32_t estimate_B;          /* 1 = after the order, estimate the causal strengths B into
                                   result.B (Alg. 1, last step); needs the full order
                                   (max_roots 0) and p <= 8000 */
-  int32_t batch_queue;         /* batches: 1 (default) = the pair and score work of every data set
-                                  on one device work queue served by a persistent grid (finished
-                                  or small sets occupy no work-groups); 0 = one grid slice per set */
+  int32_t batch_queue;         /* batches: 1 (default) = the pair work of every data set on one
+                                  device work queue served by a persistent grid (finished or small
+                                  sets occupy no work-groups); 0 = one grid slice per set.  Score
+                                  rows run in grid slices either way */
   int32_t graph;               /* batches: 1 = capture each window of 16 iterations into a HIP graph
                                   and replay it; instantiated graphs are kept for later calls with
                                   device memory at the same address and of the same layout (pass the
                                   same opts.workspace).  0 (default) = launch kernel by kernel */
   double band_target;          /* tuning: pair-samples (alive rows x targets x n) that a later
-                                  threshold band of round 0 aims at; <= 0 (default) = 6e7 for a single
-                                  MIXED / FP32_STORAGE search, 2e7 otherwise */
+                                  threshold band of round 0 aims at; <= 0 (default) = 6e7
+                                  max(1, (p/1000)^4), at most 1.6e9, for a single MIXED /
+                                  FP32_STORAGE search, 2e7 otherwise */
   int32_t first_band_blocks;   /* tuning: target blocks of an iteration's first threshold band, the
                                   later bands sized as by default (band_blocks = 0); 0 (default) = 4
                                   for a single MIXED / FP32_STORAGE search, 1 otherwise */

@@ -51,7 +51,7 @@ CHUNK_SAMPLES = 2048
 MIN_GAIN = 0.01
 SINGLE_SPACE = {
     "first_band_blocks": [1, 2, 4, 8],
-    "band_target": [1e7, 2e7, 4e7, 6e7, 1e8, 2e8, 4e8],
+    "band_target": [1e7, 2e7, 4e7, 6e7, 1e8, 2e8, 4e8, 8e8, 1.6e9],
 }
 BATCH_SPACE = dict(SINGLE_SPACE, batch_queue=[1, 0], graph=[0, 1])
 

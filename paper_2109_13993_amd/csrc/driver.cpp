@@ -372,7 +372,7 @@ struct Fit {
     const int hint = first ? (threshold ? std::min(pl.band_blocks, nb) : nb) : nb;
     BandArgs a{pl.chunk, 1, 1, BAND_TARGET_DEFAULT};
     pair_band_shape(b, a.rows_per_group, a.groups);
-    if (b.count == 1 && b.mixed) a.band_target = BAND_TARGET_SINGLE_MIXED;
+    if (b.count == 1 && b.mixed) a.band_target = band_target_single_mixed(b.p_max);
     if (o.band_target > 0.0) a.band_target = o.band_target;
     pair(t, a, first, hint);
     HIPCHK(launch_score(b, t, a, gmult, first ? 1 : 0, hint, s));

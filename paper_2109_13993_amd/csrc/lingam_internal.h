@@ -159,11 +159,21 @@ constexpr int B_MAX_P = 8000;
 // about this, rounded up to whole rounds of the work-groups when it fills
 // at least one, between band_k0 and the blocks left.  A single mixed-mode
 // search takes larger bands (its per-band overhead weighs more against its
-// fast pair kernel); FP64 searches and batches, whose launches carry more
-// work per band, take smaller ones.  Chosen by measurement at p=500,
-// n=20000 and on the batch workloads.
-constexpr double BAND_TARGET_SINGLE_MIXED = 6e7;
+// fast pair kernel): 6e7 up to p = 1000, then growing as (p / 1000)^4 up
+// to 1.6e9 (p = 1588: 3.8e8, about 1.4x faster than 6e7 on flux-like
+// stand-ins at n = 10000; up to p = 1000 larger bands lost up to 9% on
+// strongly pruned searches).  FP64 searches and batches, whose launches
+// carry more work per band, take smaller ones.  Chosen by measurement at
+// p = 100 ... 2339 and on the batch workloads.
+constexpr double BAND_TARGET_SINGLE_MIXED_MIN = 6e7;
+constexpr double BAND_TARGET_SINGLE_MIXED_MAX = 1.6e9;
 constexpr double BAND_TARGET_DEFAULT = 2e7;
+inline double band_target_single_mixed(int p) {
+  const double q = (double)p / 1000.0;
+  const double t = BAND_TARGET_SINGLE_MIXED_MIN * (q * q) * (q * q);
+  return t < BAND_TARGET_SINGLE_MIXED_MIN ? BAND_TARGET_SINGLE_MIXED_MIN
+                                          : (t > BAND_TARGET_SINGLE_MIXED_MAX ? BAND_TARGET_SINGLE_MIXED_MAX : t);
+}
 
 // Parameters of one band launch of the pair kernel.  Which target blocks
 // the band covers is decided on the device (Ctl::tb_next, ntb_next), so
