@@ -223,6 +223,8 @@ def _apply_tuned(o, kind, precision, p, n, queue=None, graph=None):
         o.first_band_blocks = int(t["first_band_blocks"])
     if o.band_target == 0.0 and "band_target" in t:
         o.band_target = float(t["band_target"])
+    if o.gamma_mult == 0.0 and "gamma_mult" in t:
+        o.gamma_mult = float(t["gamma_mult"])
     if queue is None and "batch_queue" in t:
         o.batch_queue = int(t["batch_queue"])
     if graph is None and "graph" in t and o.workspace:

@@ -1,9 +1,9 @@
 """Autotuner of the search's launch parameters on the GPU it runs on.
 
 What it tunes never changes a result: the order and every complete score
-are the same for any value (the threshold's band schedule, and for batches
-the device work queue and graph replay only move work around).  It only
-changes the time.  The sample chunk of the pair kernel's work-groups is not
+are the same for any value (the threshold's band schedule and multiplier c,
+and for batches the device work queue and graph replay, only move work
+around).  It only changes the time.  The sample chunk of the pair kernel's work-groups is not
 tuned: it groups the per-sample sums, so another chunk length rounds them
 differently, and every entry keeps the default of 2048 samples (a single
 call and a batch then give the same bits whichever entries apply).
@@ -12,6 +12,7 @@ Parameters (lingam_opts fields):
   chunk_samples  samples per pair-kernel work-group chunk (fixed at 2048)
   first_band_blocks  target blocks of an iteration's first threshold band
   band_target    pair-samples a later band of round 0 aims at
+  gamma_mult     the threshold's multiplier c between rounds (Sec. 3.2)
   batch_queue    batches: device work queue (1) or one grid slice per set (0)
   graph          batches: HIP-graph windows replayed from a workspace (1)
 
@@ -52,6 +53,7 @@ MIN_GAIN = 0.01
 SINGLE_SPACE = {
     "first_band_blocks": [1, 2, 4, 8],
     "band_target": [1e7, 2e7, 4e7, 6e7, 1e8, 2e8, 4e8, 8e8, 1.6e9],
+    "gamma_mult": [1.5, 2.0, 4.0, 8.0],
 }
 BATCH_SPACE = dict(SINGLE_SPACE, batch_queue=[1, 0], graph=[0, 1])
 
@@ -163,7 +165,7 @@ def tune_single(p: int, n: int, precision: str = "mixed", reps: int = 3, log=pri
     X = torch.from_numpy(ds.X).to("cuda:0")
     space = {k: (v[precision] if isinstance(v, dict) else v) for k, v in SINGLE_SPACE.items()}
     start = {"chunk_samples": CHUNK_SAMPLES, "first_band_blocks": 4 if precision != "fp64" else 1,
-             "band_target": 6e7 if precision != "fp64" else 2e7}
+             "band_target": 6e7 if precision != "fp64" else 2e7, "gamma_mult": 4.0}
 
     def timer(params):
         return _median_time(lambda: lg.fit_order(X, precision=precision, want_T=False, want_H=False,
@@ -196,7 +198,8 @@ def tune_batch(sets, precision: str = "mixed", reps: int = 3, log=print, path: s
     import paper_2109_13993_amd as lg
     p, n = batch_shape(sets)
     space = {k: (v[precision] if isinstance(v, dict) else v) for k, v in BATCH_SPACE.items()}
-    start = {"chunk_samples": CHUNK_SAMPLES, "first_band_blocks": 1, "band_target": 2e7, "batch_queue": 1, "graph": 0}
+    start = {"chunk_samples": CHUNK_SAMPLES, "first_band_blocks": 1, "band_target": 2e7, "gamma_mult": 4.0,
+             "batch_queue": 1, "graph": 0}
     # one workspace for every trial (the layout depends on the chunk only)
     need = lg.batch_workspace_size(sets, precision, chunk_samples=CHUNK_SAMPLES)
     ws = torch.empty(need + 4096, dtype=torch.uint8, device="cuda:0")
