@@ -200,7 +200,7 @@ struct Batch {
   int gram_slices_max = 1;
   int mixed = 0;
   int store32 = 0;           // rows stored in binary32 (every data set of the batch)
-  int queue = 1;             // batches: pair and score work on the device work queue
+  int queue = 1;             // batches: pair work on the device work queue (scores in grid slices)
   // Sets that have an iteration at t: act[0, active_at(t)) on the device;
   // act_until[i] (host, descending) is the first iteration set act[i] no
   // longer has.
