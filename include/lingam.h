@@ -73,6 +73,23 @@ typedef enum lingam_precision {
  * of variable i (Alg. 1 input).  SAMPLE_MAJOR is n x p, row k = sample k. */
 typedef enum lingam_layout { LINGAM_LAYOUT_VAR_MAJOR = 0, LINGAM_LAYOUT_SAMPLE_MAJOR = 1 } lingam_layout;
 
+/* How the tests of an iteration are mapped onto the GPU (opts.pair_strategy).
+ * DEFAULT is this library's pair kernel.  The other three are the baseline
+ * mappings the paper compares against (Sec. 5.3), kept as ablation
+ * variants: they compute the same tests (every ordered pair, FP64, without
+ * the threshold and without messaging) with a different parallel layout.
+ *   BLOCK_WORKER   one work-group per variable; its tests one after another,
+ *                  each over all samples with the whole work-group;
+ *   THREAD_WORKER  one work-group per variable; each thread one test, the
+ *                  thread walking all samples of its pair alone;
+ *   BLOCK_COMPARE  one work-group per ordered pair of variables. */
+typedef enum lingam_pair_strategy {
+  LINGAM_PAIR_DEFAULT = 0,
+  LINGAM_PAIR_BLOCK_WORKER = 1,
+  LINGAM_PAIR_THREAD_WORKER = 2,
+  LINGAM_PAIR_BLOCK_COMPARE = 3
+} lingam_pair_strategy;
+
 typedef struct lingam_opts {
   uint32_t struct_size;        /* must be sizeof(lingam_opts) */
   int32_t precision;           /* lingam_precision, default FP64 */
@@ -136,6 +153,11 @@ typedef struct lingam_opts {
                                   its exact negation (Sec. 3.1 messaging); 0 = every variable
                                   evaluates its own tests, each pair once per direction (the
                                   ablation without messaging: the same results, twice the pairs) */
+  int32_t pair_strategy;       /* lingam_pair_strategy, default DEFAULT.  The baseline strategies
+                                  need precision FP64, use_threshold = 0 and messaging = 0 (else
+                                  INVALID) and run in lingam_fit_order and lingam_fit_order_noalloc
+                                  (batches: UNSUPPORTED); results equal the default's up to the
+                                  order in which sample terms are summed */
 } lingam_opts;
 
 /* Outputs.  All arrays are host memory owned by the caller; NULL = not wanted. */

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "liblingam.so")
 OK, E_INVALID, E_NONFINITE, E_DEGENERATE, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(7)
 PREC = {"fp64": 0, "mixed": 1, "fp32": 1, "fp32_storage": 2}
 LAYOUT = {"var_major": 0, "sample_major": 1}
+PAIR_STRATEGY = {"default": 0, "block_worker": 1, "thread_worker": 2, "block_compare": 3}
 
 # Exported symbols of the C ABI (kept in sync with include/lingam.h).
 SYMBOLS = ("lingam_opts_default", "lingam_fit_order", "lingam_fit_order_noalloc", "lingam_fit_order_batch",
@@ -57,6 +58,7 @@ class LingamOpts(ctypes.Structure):
         ("band_target", ctypes.c_double),
         ("first_band_blocks", ctypes.c_int32),
         ("messaging", ctypes.c_int32),
+        ("pair_strategy", ctypes.c_int32),
     ]
 
 
@@ -238,7 +240,7 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
               layout: str = "var_major", stream=None, profile: bool = False,
               workspace=None, noalloc: bool = False, estimate_B: bool = False,
               band_target: float = 0.0, first_band_blocks: int = 0, tune: bool = True,
-              messaging: bool = True) -> FitResult:
+              messaging: bool = True, pair_strategy: str = "default") -> FitResult:
     """Causal order of the variables of X (lingam_fit_order).
 
     X is a p x n array (row i = samples of variable i; layout="sample_major"
@@ -251,6 +253,10 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
     noalloc: call lingam_fit_order_noalloc, which carves every buffer from the
     library's fixed per-GPU device array and allocates nothing.
     estimate_B: also estimate the causal strengths B from the order (result.B).
+    pair_strategy: "default", or one of the paper's baseline mappings of the
+    tests (Sec. 5.3) kept as ablations -- "block_worker", "thread_worker",
+    "block_compare" -- which need precision="fp64", use_threshold=False and
+    messaging=False.
     band_target / chunk_samples / band_blocks: launch tuning (never changes a
     result); left at 0 they take the autotuner's entry for this device and
     problem bucket when there is one (tune=True), else the library defaults.
@@ -295,6 +301,7 @@ def fit_order(X, precision: str = "fp64", use_threshold: bool = True, gamma0: fl
     o.band_target = float(band_target)
     o.first_band_blocks = int(first_band_blocks)
     o.messaging = 1 if messaging else 0
+    o.pair_strategy = PAIR_STRATEGY[pair_strategy]
     if tune:
         _apply_tuned(o, "single", precision, p, n)
     order = np.full(p, -1, dtype=np.int32)

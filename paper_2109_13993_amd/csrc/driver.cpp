@@ -167,6 +167,11 @@ lingam_status validate_opts(const lingam_opts& o) {
   if (o.band_blocks < 0) return fail(LINGAM_E_INVALID, "band_blocks < 0");
   if (o.first_band_blocks < 0) return fail(LINGAM_E_INVALID, "first_band_blocks < 0");
   if (o.messaging != 0 && o.messaging != 1) return fail(LINGAM_E_INVALID, "messaging must be 0 or 1");
+  if (o.pair_strategy < LINGAM_PAIR_DEFAULT || o.pair_strategy > LINGAM_PAIR_BLOCK_COMPARE)
+    return fail(LINGAM_E_INVALID, "unknown pair_strategy");
+  if (o.pair_strategy != LINGAM_PAIR_DEFAULT &&
+      (o.precision != LINGAM_PREC_FP64 || o.use_threshold || o.messaging))
+    return fail(LINGAM_E_INVALID, "a baseline pair_strategy needs FP64, use_threshold = 0 and messaging = 0");
   if (o.record_M_iters < 0) return fail(LINGAM_E_INVALID, "record_M_iters < 0");
   if (o.estimate_B != 0 && o.estimate_B != 1) return fail(LINGAM_E_INVALID, "estimate_B must be 0 or 1");
   if (o.batch_queue != 0 && o.batch_queue != 1) return fail(LINGAM_E_INVALID, "batch_queue must be 0 or 1");
@@ -356,6 +361,10 @@ struct Fit {
   int refresh_every = 1;     // Gram refresh period (0 = the rank-1 recursion only)
 
   void pair(int t, const BandArgs& a, bool dense, int ntb_hint) {
+    if (o.pair_strategy != LINGAM_PAIR_DEFAULT) {
+      HIPCHK(launch_pair_baseline(b, t, o.pair_strategy, a.chunk, s));
+      return;
+    }
     if (timer && timer->on) {
       hipEvent_t e0 = timer->next(), e1 = timer->next();
       HIPCHK(launch_pair_band(b, t, a, dense ? 1 : 0, ntb_hint, s, e0, e1));
@@ -822,7 +831,7 @@ uint64_t batch_layout_key(const char* base, uint64_t bytes, int32_t count, const
   const uint64_t fields[] = {(uint64_t)o.precision, (uint64_t)o.use_threshold, (uint64_t)o.max_roots,
                              (uint64_t)o.batch_queue, (uint64_t)refresh_every, (uint64_t)pl.chunk,
                              (uint64_t)pl.band_blocks, (uint64_t)o.band_blocks, (uint64_t)o.first_band_blocks,
-                             (uint64_t)o.x_dtype, (uint64_t)o.messaging,
+                             (uint64_t)o.x_dtype, (uint64_t)o.messaging, (uint64_t)o.pair_strategy,
                              (uint64_t)o.layout, (uint64_t)o.x_on_device};
   for (uint64_t v : fields) h = mix64(h, v);
   uint64_t g0, gm, bt;
@@ -878,6 +887,8 @@ lingam_status validate_batch(int32_t count, const lingam_dataset* sets, const li
   if (st != LINGAM_OK) return st;
   if (o.forced_len > 0 || o.record_M_iters > 0 || o.estimate_B)
     return fail(LINGAM_E_UNSUPPORTED, "forced_order, record_M_iters and estimate_B are not available in batches");
+  if (o.pair_strategy != LINGAM_PAIR_DEFAULT)
+    return fail(LINGAM_E_UNSUPPORTED, "the baseline pair strategies are not available in batches");
   for (int k = 0; k < count; ++k) {
     const lingam_dataset& ds = sets[k];
     if (!ds.X) return fail(LINGAM_E_INVALID, "data set with X == NULL");

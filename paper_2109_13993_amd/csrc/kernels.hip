@@ -1208,6 +1208,163 @@ hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense,
 }
 
 // ============================================================================
+// f3: the paper's baseline mappings of the tests onto the GPU (Sec. 5.3),
+// as ablation variants of the pair step (FP64, every ordered pair, no
+// threshold and no messaging)
+// ============================================================================
+// Each computes, for every ordered pair (x, w) of the remaining variables,
+// the chunk partial sums that the pair kernel would write with messaging
+// off -- sum(log cosh u + ln 2) and sum(u exp(-u^2/2)) of r_x^(w) and of
+// r_w^(x), per chunk of `chunk` samples -- and marks the test pending; the
+// score kernel then forms the tests exactly as after the pair kernel.  They
+// differ only in how the work is mapped:
+//   block worker   one work-group per variable x, which takes its tests one
+//                  after another, each over all samples with the whole
+//                  group (memory O(rn): only the two rows of the test);
+//   thread worker  one work-group per variable x, each thread one test,
+//                  the thread walking all samples of its pair alone;
+//   block compare  one work-group per ordered pair, over all samples.
+// The residual and its scale come from the covariance and row scales as in
+// the pair kernel (the rows are already centred and scaled), so nothing is
+// recomputed per test beyond the sample sums.
+
+// The pair's regression coefficient b and residual scale 1/sqrt(1 - b^2),
+// formed as the pair kernel forms them; false for a degenerate pair
+// (1 - b^2 <= DEGEN_EPS), which the caller reports.
+__device__ __forceinline__ bool baseline_coef(const Dev& d, int t, int x, int w, double& b, double& sc) {
+  const int buf = t & 1;
+  const int p = d.p;
+  const double* dsc = d.dsc[buf];
+  b = d.Sig[buf][(int64_t)x * p + w] * (dsc[x] * dsc[w]);
+  const double om = 1.0 - b * b;
+  if (!(om > DEGEN_EPS)) return false;
+  sc = rsqrt(om);
+  return true;
+}
+
+__device__ __forceinline__ void baseline_degenerate(const Dev& d, int t, int x, int w) {
+  raise_error(d.ctl, ST_DEGENERATE, d.idx[t & 1][x], d.idx[t & 1][w]);
+}
+
+__device__ __forceinline__ void baseline_store(const Dev& d, int x, int w, int c, double a0, double a1, double a2,
+                                               double a3) {
+  const int p = d.p;
+  double* q = d.P + (((int64_t)c * p + x) * p + w) * 4;
+  q[0] = a0;
+  q[1] = a1;
+  q[2] = a2;
+  q[3] = a3;
+}
+
+// Test (x, w) by one work-group of 256 threads: per chunk, the threads
+// stride over its samples and the four sums are reduced over the group.
+__device__ __forceinline__ void baseline_pair_group(const Dev& d, int t, int x, int w, int chunk) {
+  __shared__ double sh[4];
+  double b = 0.0, sc = 1.0;
+  if (!baseline_coef(d, t, x, w, b, sc)) {   // the same for every thread
+    if (threadIdx.x == 0) baseline_degenerate(d, t, x, w);
+    return;
+  }
+  const double* Z = static_cast<const double*>(d.Z[t & 1]);
+  const double* zx = Z + (int64_t)x * d.ldz;
+  const double* zw = Z + (int64_t)w * d.ldz;
+  const int64_t n = d.n;
+  for (int c = 0; c < d.nchunk; ++c) {
+    const int64_t k1 = min(n, (int64_t)(c + 1) * chunk);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int64_t k = (int64_t)c * chunk + threadIdx.x; k < k1; k += 256) {
+      const double rv = __builtin_fma(-b, zw[k], zx[k]);   // r_x^(w) / s
+      const double rw = __builtin_fma(-b, zx[k], zw[k]);   // r_w^(x) / s
+      terms_f64(sc * rv, a0, a1);
+      terms_f64(sc * rw, a2, a3);
+    }
+    a0 = block_sum256(a0, sh);
+    a1 = block_sum256(a1, sh);
+    a2 = block_sum256(a2, sh);
+    a3 = block_sum256(a3, sh);
+    if (threadIdx.x == 0) baseline_store(d, x, w, c, a0, a1, a2, a3);
+  }
+  if (threadIdx.x == 0) d.pend[(int64_t)x * d.p + w] = 1;
+}
+
+__device__ __forceinline__ void baseline_count(const Dev& d, unsigned long long pairs, int64_t where) {
+  if (pairs == 0) return;
+  const int slot = (int)(where % PAIR_SLOTS);
+  atomicAdd(&d.pair_slots[slot], pairs);
+  atomicAdd(&d.pair_slots[PAIR_SLOTS + slot], pairs);
+}
+
+__global__ __launch_bounds__(256) void k_block_worker(const Dev d, int t, int chunk) {
+  const int r = rows_left(d, t);
+  if (r < 2 || halted(d.ctl) || d.ctl->done) return;
+  const int x = blockIdx.x;
+  for (int w = 0; w < r; ++w)
+    if (w != x) baseline_pair_group(d, t, x, w, chunk);
+  if (threadIdx.x == 0) baseline_count(d, (unsigned long long)(r - 1), x);
+}
+
+__global__ __launch_bounds__(256) void k_thread_worker(const Dev d, int t, int chunk) {
+  const int r = rows_left(d, t);
+  if (r < 2 || halted(d.ctl) || d.ctl->done) return;
+  const int x = blockIdx.x;
+  const double* Z = static_cast<const double*>(d.Z[t & 1]);
+  const double* zx = Z + (int64_t)x * d.ldz;
+  const int64_t n = d.n;
+  unsigned long long pairs = 0;
+  for (int w = threadIdx.x; w < r; w += 256) {
+    double b = 0.0, sc = 1.0;
+    if (w == x) continue;
+    if (!baseline_coef(d, t, x, w, b, sc)) {
+      baseline_degenerate(d, t, x, w);
+      continue;
+    }
+    const double* zw = Z + (int64_t)w * d.ldz;
+    for (int c = 0; c < d.nchunk; ++c) {
+      const int64_t k1 = min(n, (int64_t)(c + 1) * chunk);
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      for (int64_t k = (int64_t)c * chunk; k < k1; ++k) {
+        const double rv = __builtin_fma(-b, zw[k], zx[k]);
+        const double rw = __builtin_fma(-b, zx[k], zw[k]);
+        terms_f64(sc * rv, a0, a1);
+        terms_f64(sc * rw, a2, a3);
+      }
+      baseline_store(d, x, w, c, a0, a1, a2, a3);
+    }
+    d.pend[(int64_t)x * d.p + w] = 1;
+    ++pairs;
+  }
+  baseline_count(d, pairs, (int64_t)x * 256 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_block_compare(const Dev d, int t, int chunk) {
+  const int r = rows_left(d, t);
+  const int x = blockIdx.y, w = blockIdx.x;
+  if (x == w || r < 2 || halted(d.ctl) || d.ctl->done) return;
+  baseline_pair_group(d, t, x, w, chunk);
+  if (threadIdx.x == 0) baseline_count(d, 1ull, (int64_t)x * r + w);
+}
+
+hipError_t launch_pair_baseline(const Batch& b, int t, int strategy, int chunk, hipStream_t s) {
+  const int r = b.p_max - t;
+  if (r < 2) return hipSuccess;
+  if (b.count != 1 || b.store32 || b.mixed) return hipErrorInvalidValue;   // FP64 single searches only
+  switch (strategy) {
+    case LINGAM_PAIR_BLOCK_WORKER:
+      hipLaunchKernelGGL(k_block_worker, dim3(r), dim3(256), 0, s, b.one, t, chunk);
+      break;
+    case LINGAM_PAIR_THREAD_WORKER:
+      hipLaunchKernelGGL(k_thread_worker, dim3(r), dim3(256), 0, s, b.one, t, chunk);
+      break;
+    case LINGAM_PAIR_BLOCK_COMPARE:
+      hipLaunchKernelGGL(k_block_compare, dim3(r, r), dim3(256), 0, s, b.one, t, chunk);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ============================================================================
 // a5/a6: tests, scores, threshold state, termination and root
 // ============================================================================
 // Iteration-level decision after a band, taken by one work-group of 256

@@ -234,6 +234,9 @@ void pair_band_shape(const Batch& b, int& rows_per_group, int& groups);
 // itself (nullptr: an untimed launch).
 hipError_t launch_pair_band(const Batch& b, int t, const BandArgs& a, int dense, int ntb_hint, hipStream_t s,
                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// The tests of iteration t by one of the baseline mappings (lingam_pair_strategy 1-3):
+// FP64 single searches, every ordered pair, chunk partials of `chunk` samples.
+hipError_t launch_pair_baseline(const Batch& b, int t, int strategy, int chunk, hipStream_t s);
 hipError_t launch_score(const Batch& b, int t, const BandArgs& a, double gamma_mult, int dense, int ntb_hint,
                         hipStream_t s);
 hipError_t launch_window_reset(const Batch& b, hipStream_t s);

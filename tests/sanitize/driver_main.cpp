@@ -92,6 +92,27 @@ int main() {
         expect(lingam_fit_order(src, n, p, &q, &out.r), LINGAM_E_INVALID, "misaligned workspace");
         std::free(ws);
       }
+    // the baseline pair strategies (FP64, no threshold, no messaging), and
+    // the combinations they refuse
+    for (int strategy = LINGAM_PAIR_BLOCK_WORKER; strategy <= LINGAM_PAIR_BLOCK_COMPARE; ++strategy) {
+      lingam_opts q = o;
+      q.pair_strategy = strategy;
+      q.use_threshold = 0;
+      q.messaging = 0;
+      Out out(p, 0);
+      expect(lingam_fit_order(X.data(), n, p, &q, &out.r), LINGAM_OK, "baseline strategy");
+      q.use_threshold = 1;
+      expect(lingam_fit_order(X.data(), n, p, &q, &out.r), LINGAM_E_INVALID, "baseline with threshold");
+      q.use_threshold = 0;
+      q.precision = LINGAM_PREC_MIXED;
+      expect(lingam_fit_order(X.data(), n, p, &q, &out.r), LINGAM_E_INVALID, "baseline in mixed precision");
+    }
+    {
+      lingam_opts q = o;
+      q.pair_strategy = 4;
+      Out out(p, 0);
+      expect(lingam_fit_order(X.data(), n, p, &q, &out.r), LINGAM_E_INVALID, "unknown strategy");
+    }
     // step 2 on its own
     std::vector<int32_t> ord(p);
     for (int64_t k = 0; k < p; ++k) ord[k] = (int32_t)(p - 1 - k);
@@ -209,6 +230,11 @@ int main() {
     std::vector<Out> outs;
     for (int k = 0; k < count; ++k) { outs.emplace_back(sets[k].p, 0, false); rs[k] = outs.back().r; }
     expect(lingam_fit_order_batch(count, sets.data(), &q, rs.data()), LINGAM_E_UNSUPPORTED, "batch record_M");
+    q = o;
+    q.pair_strategy = LINGAM_PAIR_BLOCK_COMPARE;
+    q.use_threshold = 0;
+    q.messaging = 0;
+    expect(lingam_fit_order_batch(count, sets.data(), &q, rs.data()), LINGAM_E_UNSUPPORTED, "batch baseline strategy");
     expect(lingam_fit_order_batch(0, sets.data(), &o, rs.data()), LINGAM_E_INVALID, "batch of 0");
     std::vector<int64_t> badidx = {0, 1, 500};
     lingam_dataset bad = {base.data(), 500, 12, badidx.data(), 3};

@@ -193,6 +193,7 @@ void pair_band_shape(const Batch&, int& rows_per_group, int& groups) {
 hipError_t launch_pair_band(const Batch&, int, const BandArgs&, int, int, hipStream_t, hipEvent_t, hipEvent_t) {
   return hipSuccess;
 }
+hipError_t launch_pair_baseline(const Batch&, int, int, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_score(const Batch&, int, const BandArgs&, double, int, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_window_reset(const Batch&, hipStream_t) { return hipSuccess; }
 hipError_t launch_record_M(const Batch&, int, hipStream_t) { return hipSuccess; }

@@ -126,6 +126,24 @@ def test_invalid_arguments_rejected_before_device_work(lib):
         assert st == lg.E_INVALID and "forced" in msg
 
 
+def test_baseline_pair_strategies_validated_before_device_work(lib):
+    # the paper's baseline mappings (ablation variants) evaluate every ordered
+    # pair in FP64: the threshold, messaging and the binary32 modes are refused
+    X = np.zeros((4, 10))
+    for strategy in (1, 2, 3):
+        o = lg.default_opts(); o.pair_strategy = strategy
+        st, msg = _call(X, 10, 4, o)                         # threshold and messaging on
+        assert st == lg.E_INVALID and "pair_strategy" in msg
+        o.use_threshold = 0
+        assert _call(X, 10, 4, o)[0] == lg.E_INVALID       # messaging still on
+        o.messaging = 0; o.precision = lg.PREC["mixed"]
+        assert _call(X, 10, 4, o)[0] == lg.E_INVALID
+    for bad in (-1, 4):
+        o = lg.default_opts(); o.pair_strategy = bad
+        st, msg = _call(X, 10, 4, o)
+        assert st == lg.E_INVALID and "pair_strategy" in msg
+
+
 def test_batch_entry_point_reports_status(lib):
     res = (lg.LingamResult * 1)()
     st = lib.lingam_fit_order_batch(0, None, None, res)
