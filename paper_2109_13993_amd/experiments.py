@@ -15,6 +15,17 @@
                (synth.flux_like_dataset, rows near the null space of a sparse
                stoichiometric-like matrix) at the real sets' p and n = 10000,
                and the exactly collinear case, which must end DEGENERATE.
+  baselines    Sec. 5.3 (Fig. 3): the paper's baseline mappings of the tests
+               (block worker, thread worker, block compare; FP64, every
+               ordered pair) against this library's FP64 search, on the
+               flux-like stand-ins: the full order time of each, the speedup
+               of the library over each, and the same pair kernel without the
+               threshold and messaging (which separates the mapping from the
+               pairs the paper's method avoids).  A baseline whose time,
+               extrapolated as p^3 from the previous stand-in, would exceed
+               `max_seconds` is skipped and reported as such.  Names are
+               those of the flux data sets, or p<k> for a stand-in of k
+               variables.
 
 Each prints JSON lines on stdout (one per measurement); times are wall
 times of lingam_fit_order on device-resident input, median of `reps`.
@@ -119,22 +130,58 @@ def flux(names=None, n=10000, precisions=("mixed",), reps=1):
            "status": status})
 
 
+def baselines(names=("ecoli_core", "iJR904"), n=10000, reps=1, max_seconds=120.0):
+    import torch
+    import paper_2109_13993_amd as lg
+    from paper_2109_13993_amd import synth
+    last = {}
+    for name in names:
+        # a named data set's size, or "p<k>" for a flux-like stand-in of k variables
+        p = synth.FLUX_P[name] if name in synth.FLUX_P else int(name.lstrip("p"))
+        ds = synth.flux_like_dataset(p, n, np.random.default_rng([5, 6, p]))
+        X = torch.from_numpy(ds.X).to("cuda:0")
+        base_kw = dict(precision="fp64", want_T=False, want_H=False)
+        t_lib, r_lib = _timed(lambda: lg.fit_order(X, **base_kw), reps)
+        runs = [("library (threshold, messaging)", t_lib, r_lib)]
+        flat = dict(base_kw, use_threshold=False, messaging=False)
+        t_flat, r_flat = _timed(lambda: lg.fit_order(X, **flat), reps)
+        runs.append(("library pair kernel, every ordered pair", t_flat, r_flat))
+        for s in ("block_worker", "thread_worker", "block_compare"):
+            if s in last:
+                p0, t0 = last[s]
+                if t0 * (p / p0) ** 3 > max_seconds:
+                    _emit({"experiment": "baselines", "stand_in_for": name, "p": p, "n": n, "strategy": s,
+                           "status": "skipped", "extrapolated_seconds": t0 * (p / p0) ** 3})
+                    continue
+            t, r = _timed(lambda: lg.fit_order(X, pair_strategy=s, **flat), reps)
+            last[s] = (p, t)
+            runs.append((s, t, r))
+        for label, t, r in runs:
+            _emit({"experiment": "baselines", "stand_in_for": name, "p": p, "n": n, "strategy": label,
+                   "status": "ok", "seconds": t, "pairs_evaluated": r.pairs_evaluated,
+                   "library_speedup": t / t_lib, "order_equals_library": bool(np.array_equal(r.order, r_lib.order))})
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("which", choices=["scalability", "ablation", "flux"])
+    ap.add_argument("which", choices=["scalability", "ablation", "flux", "baselines"])
     ap.add_argument("--p", type=int, default=500)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "fp32_storage"])
     ap.add_argument("--dense", action="store_true")
     ap.add_argument("--reps", type=int, default=3)
-    ap.add_argument("--names", default=None, help="flux: comma-separated data-set names")
+    ap.add_argument("--names", default=None, help="flux, baselines: comma-separated data-set names")
+    ap.add_argument("--max-seconds", type=float, default=120.0, help="baselines: skip longer extrapolated runs")
     a = ap.parse_args()
     if a.which == "scalability":
         scalability(reps=a.reps)
     elif a.which == "ablation":
         ablation(a.p, a.n, a.precision, a.reps, a.dense)
-    else:
+    elif a.which == "flux":
         flux(a.names.split(",") if a.names else None, reps=max(1, a.reps // 3))
+    else:
+        baselines(tuple(a.names.split(",")) if a.names else ("ecoli_core", "iJR904"), reps=max(1, a.reps // 3),
+                  max_seconds=a.max_seconds)
 
 
 if __name__ == "__main__":
