@@ -326,6 +326,35 @@ def test_many_variables_first_roots():
     assert list(gm.order[:4]) == list(g.order[:4])
 
 
+def test_more_rows_than_the_rank_kernel_orders():
+    # p=16500 > 16384: past the rank kernel's limit the positions keep the
+    # original order; every index offset into the p x p matrices exceeds 2^28.
+    # Two iterations of the FP64 search without the threshold (every pair in
+    # one band); at each, the oracle scores the GPU root and 5 sampled
+    # variables (with the GPU's root prefix): the scores must agree and the
+    # root's must be the largest.  Independent rows of uniform noise with a
+    # few planted edges keep the data cheap to make at this size.
+    p, n = 16500, 256
+    rng = np.random.default_rng(165)
+    X = rng.uniform(-1.0, 1.0, size=(p, n))
+    for k in range(0, 40, 2):
+        X[k + 1] += 0.8 * X[k]
+    g = lg.fit_order(X, precision="fp64", use_threshold=False, max_roots=2, want_H=False)
+    for t in range(2):
+        prefix = [int(v) for v in g.order[:t]]
+        root = int(g.order[t])
+        rest = sorted(set(range(p)) - set(prefix) - {root})
+        vars_ = sorted([root] + rng.choice(rest, 5, replace=False).tolist())
+        T, _ = oracle.sampled_at(X, prefix, t, vars=vars_, pairs=[])
+        T = np.asarray(T)
+        got = g.T[t, vars_]
+        rel = np.abs(got - T) / np.maximum(np.abs(T), 1e-12)
+        _log("p=16500 t=%d root %d: max rel |dT| %.2e" % (t, root, rel.max()))
+        assert rel.max() < 1e-8
+        others = np.delete(T, vars_.index(root))
+        assert np.all(T[vars_.index(root)] >= others - 1e-8 * np.abs(others) - 1e-15)
+
+
 def test_fullsize_runs_are_deterministic_and_threshold_exact(cfg3):
     X = cfg3.X
     a = lg.fit_order(X, precision="mixed")
