@@ -320,7 +320,7 @@ Dev carve_set(Arena& al, int64_t n, int64_t p, const Plan& pl, const lingam_opts
   d.Mrec = d.rec > 0 ? al.get<double>((size_t)d.rec * pp) : nullptr;
   d.stats = al.get<double>(2 * P);
   d.gram_slices_max = GRAM_SLICES_MAX;
-  d.Gp = al.get<double>((size_t)GRAM_SLICES_MAX * pp);
+  d.Gp = al.get<double>((size_t)gram_partial_rows(p, n, GRAM_SLICES_MAX) * (size_t)p);
   d.forced_len = o.forced_len;
   int32_t* forced_dev = al.get<int32_t>(std::max<size_t>(1, (size_t)o.forced_len));
   d.forced = forced_dev;

@@ -305,23 +305,8 @@ hipError_t launch_gather(const double* X, int64_t n_src, int64_t p, const int64_
 // a2: CalculateCovMat / refresh -- Sigma = Z Z^T / (n-1) on the FP64 matrix cores
 // ============================================================================
 typedef double dbl4 __attribute__((ext_vector_type(4)));
-constexpr int GT = 32;   // output tile (GT x GT) per work-group, 4 waves of 16 x 16
-constexpr int GK = 64;   // samples per LDS stage
-
-// Sample slices of the split Gram for r rows and n samples: enough work-
-// groups to fill the device, each slice at least four LDS stages long.
-__host__ __device__ inline int gram_slices(int r, int64_t n, int max_slices) {
-  const int nt = (r + GT - 1) / GT;
-  const int tiles = nt * (nt + 1) / 2;
-  int sl = (2048 + tiles - 1) / tiles;
-  const int64_t stages = (n + GK - 1) / GK;
-  const int64_t cap = stages / 4 > 1 ? stages / 4 : 1;
-  if ((int64_t)sl > cap) sl = (int)cap;
-  if (sl > max_slices) sl = max_slices;
-  return sl < 1 ? 1 : sl;
-}
-
 // Partial Gram of one sample slice: Gp[slice][i][j] = sum_{k in slice} z_i[k] z_j[k]
+// (slice stride r rows of p: the buffer holds the most slices times rows any r needs)
 // for the upper-triangular 32 x 32 tile given by blockIdx.x (i <= j).  Each
 // LDS stage is summed by the matrix cores into a fresh accumulator and then
 // added into a Kahan-compensated total; the next stage is fetched into
@@ -407,7 +392,7 @@ __device__ __forceinline__ void k_gram_partial_body(const Dev& d, int buf, int t
     __syncthreads();
   }
   // result layout of v_mfma_f64_16x16x4f64: lane holds rows lane/16 + 4v, column lane%16
-  double* G = Gp + (int64_t)blockIdx.y * ldg * ldg;
+  double* G = Gp + (int64_t)blockIdx.y * r * ldg;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int gi = i0 + wy * 16 + (lane >> 4) + 4 * v;
@@ -439,7 +424,7 @@ __device__ __forceinline__ void k_gram_reduce_body(const Dev& d, int buf, int t)
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (i >= r || j < i || j >= r) return;
   double sum = 0.0;
-  for (int q = 0; q < nslice; ++q) sum += Gp[((int64_t)q * ldg + i) * ldg + j];
+  for (int q = 0; q < nslice; ++q) sum += Gp[((int64_t)q * r + i) * ldg + j];
   const double val = sum / (n - 1.0);
   Sig[(int64_t)i * ldg + j] = val;
   Sig[(int64_t)j * ldg + i] = val;

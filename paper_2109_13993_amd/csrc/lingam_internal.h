@@ -38,6 +38,33 @@ constexpr int CHUNK_DEFAULT = 2048;
 constexpr int CHUNK_MAX_MIXED = 2048;
 // Degeneracy guard on 1 - corr^2 of an evaluated pair (and row variance).
 constexpr double DEGEN_EPS = 1e-12;
+
+// The split Gram (CalculateCovMat and its refreshes): output tiles of GT x GT
+// per work-group, GK samples per LDS stage, and a split of the samples into
+// slices with enough work-groups to fill the device, each slice at least
+// four stages long.
+constexpr int GT = 32;
+constexpr int GK = 64;
+constexpr int gram_slices(int r, int64_t n, int max_slices) {
+  const int nt = (r + GT - 1) / GT;
+  const int tiles = nt * (nt + 1) / 2;
+  int sl = (2048 + tiles - 1) / tiles;
+  const int64_t stages = (n + GK - 1) / GK;
+  const int64_t cap = stages / 4 > 1 ? stages / 4 : 1;
+  if ((int64_t)sl > cap) sl = (int)cap;
+  if (sl > max_slices) sl = max_slices;
+  return sl < 1 ? 1 : sl;
+}
+// Rows of partial sums the Gram of r <= p rows needs at most (slices x r),
+// over every r: the partial-sum buffer holds this many rows of p.
+inline int64_t gram_partial_rows(int64_t p, int64_t n, int max_slices) {
+  int64_t most = 0;
+  for (int64_t r = 1; r <= p; ++r) {
+    const int64_t v = (int64_t)gram_slices((int)r, n, max_slices) * r;
+    if (v > most) most = v;
+  }
+  return most;
+}
 constexpr int PAIR_SLOTS = 2048;
 // Sample segments of a row in the row update (one work-group each); with no
 // Gram refresh between two iterations the update also sums the new row's
@@ -143,7 +170,7 @@ struct Dev {
   const int32_t* forced = nullptr;  // device copy of the forced prefix
   int forced_len = 0;
   double* stats = nullptr;   // [2*p] per-row mean/variance of the input (diagnostics)
-  double* Gp = nullptr;      // [gram_slices_max][p][p] per-slice partial Gram
+  double* Gp = nullptr;      // [slices][r][p] per-slice partial Gram (gram_partial_rows x p)
   int gram_slices_max = 1;   // largest sample split of the Gram
   // causal strengths from the order (Alg. 1, last step), when asked for
   double* C0 = nullptr;      // p x p correlation of the normalised input
