@@ -341,7 +341,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 searches (default: min(steps, 3))")
-    ap.add_argument("--cpu-vars", type=int, default=160, help="variables in the CPU-oracle sample")
+    ap.add_argument("--cpu-vars", type=int, default=450, help="variables in the CPU-oracle sample (about 12 s on 16 threads)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 and binary32-storage searches")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-search workloads")
