@@ -1359,8 +1359,11 @@ hipError_t launch_pair_baseline(const Batch& b, int t, int strategy, int chunk, 
 // complete score (with its lowest original index) and the smallest incomplete one;
 // for a threshold gamma, some complete score is <= gamma iff the first is,
 // and some incomplete one iff the second is, so the threshold loop needs no
-// further pass.
-__device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__ alive,
+// further pass.  A band that leaves every score above gamma ends its round
+// at once: with no variable below the threshold the round's later bands
+// would compare nothing and leave every score as it is, so their decisions
+// would see these scores again.  Returns 1 when the round ended.
+__device__ int decide_group(const double* __restrict__ S, uint8_t* __restrict__ alive,
                              const uint8_t* __restrict__ complete, int32_t* __restrict__ alive_list, int r,
                              int round_end, int t, double gamma_mult, const int32_t* __restrict__ forced,
                              int forced_len, const int32_t* __restrict__ idx, Ctl* ctl) {
@@ -1427,7 +1430,11 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
     const bool cand = (has & 1) && minc <= gamma;
     const bool blocked = (has & 2) && mini <= gamma;
     if (cand && !blocked) { done = 1; break; }
-    if (round_end && !cand && !blocked) { gamma = gamma > 0.0 ? gamma * gamma_mult : 1e-300; continue; }
+    if (!cand && !blocked) {
+      round_end = 1;
+      gamma = gamma > 0.0 ? gamma * gamma_mult : 1e-300;
+      continue;
+    }
     break;
   }
   const int root = !done ? -1 : (want >= 0 ? pos : (ci == 0x7fffffff ? -1 : ci));
@@ -1468,6 +1475,7 @@ __device__ void decide_group(const double* __restrict__ S, uint8_t* __restrict__
     ctl->bands_total += 1;
     ctl->iter_bands += 1;
   }
+  return round_end;
 }
 
 // The rows whose tests can have changed in the current band: the variables
@@ -1642,9 +1650,10 @@ __device__ __forceinline__ void band_decision(const Dev& d, int t, const BandArg
   }
   __syncthreads();
   const int tb0 = s_tb0, ntb = s_ntb;
-  const int round_end = tb0 + ntb >= nb ? 1 : 0;  // the last band of the round
-  decide_group(d.S, d.alive, d.complete, d.alive_list, r, round_end, t, gamma_mult, d.forced, d.forced_len,
-               d.idx[buf], ctl);
+  // the last band of the round, or a band after which no variable is left
+  // below the threshold
+  const int round_end = decide_group(d.S, d.alive, d.complete, d.alive_list, r, tb0 + ntb >= nb ? 1 : 0, t,
+                                     gamma_mult, d.forced, d.forced_len, d.idx[buf], ctl);
   if (threadIdx.x == 0 && !ctl->done && ctl->status == ST_OK) {
     // the next band: after the end of a round every block at once; within
     // round 0 the following blocks, as many as bring the band near the
