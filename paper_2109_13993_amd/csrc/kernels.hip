@@ -1376,12 +1376,13 @@ __device__ int decide_group(const double* __restrict__ S, uint8_t* __restrict__ 
   // (ties go to the lowest original index); has: bit 0 some complete row,
   // bit 1 some incomplete row
   int ci = 0x7fffffff, cix = 0x7fffffff, pos = -1, has = 0;
-  // the scores of the first KC * 256 positions stay in registers for the
-  // compaction below
+  // the scores and complete flags of the first KC * 256 positions stay in
+  // registers for the compaction below
   constexpr int KC = 8;
   double sv[KC];
-  auto visit = [&](int y, double sy) {
-    if (complete[y]) {
+  bool cv[KC];
+  auto visit = [&](int y, double sy, bool cy) {
+    if (cy) {
       has |= 1;
       const int iy = idx[y];
       if (sy < minc || (sy == minc && iy < cix)) { minc = sy; ci = y; cix = iy; }
@@ -1395,13 +1396,14 @@ __device__ int decide_group(const double* __restrict__ S, uint8_t* __restrict__ 
   for (int k = 0; k < KC; ++k) {
     const int y = tid + 256 * k;
     sv[k] = y < r ? S[y] : INFINITY;
+    cv[k] = y < r ? complete[y] != 0 : true;
   }
 #pragma unroll
   for (int k = 0; k < KC; ++k) {
     const int y = tid + 256 * k;
-    if (y < r) visit(y, sv[k]);
+    if (y < r) visit(y, sv[k], cv[k]);
   }
-  for (int y = tid + 256 * KC; y < r; y += 256) visit(y, S[y]);
+  for (int y = tid + 256 * KC; y < r; y += 256) visit(y, S[y], complete[y] != 0);
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     const double oc = __shfl_xor(minc, off, 64);
@@ -1439,10 +1441,14 @@ __device__ int decide_group(const double* __restrict__ S, uint8_t* __restrict__ 
   }
   const int root = !done ? -1 : (want >= 0 ? pos : (ci == 0x7fffffff ? -1 : ci));
   // threshold state for the next band and the compacted alive list, in
-  // ascending position
+  // ascending position.  The list holds the variables below the threshold
+  // that still have a test to evaluate: a complete variable has none, so it
+  // would bring only items that leave at their mask test, and its score no
+  // longer changes (it still counts for the termination test above, which
+  // reads every score).
   int base = 0;
-  auto compact = [&](int y, double sy) {
-    const int a = y < r && sy <= gamma ? 1 : 0;
+  auto compact = [&](int y, double sy, bool cy) {
+    const int a = y < r && sy <= gamma && !cy ? 1 : 0;
     if (y < r) alive[y] = (uint8_t)a;
     const unsigned long long bal = __ballot(a);
     if (lane == 0) sh_cnt[wv] = __popcll(bal);
@@ -1456,8 +1462,11 @@ __device__ int decide_group(const double* __restrict__ S, uint8_t* __restrict__ 
   };
 #pragma unroll
   for (int k = 0; k < KC; ++k)
-    if (256 * k < r) compact(tid + 256 * k, sv[k]);
-  for (int y0 = 256 * KC; y0 < r; y0 += 256) compact(y0 + tid, y0 + tid < r ? S[y0 + tid] : INFINITY);
+    if (256 * k < r) compact(tid + 256 * k, sv[k], cv[k]);
+  for (int y0 = 256 * KC; y0 < r; y0 += 256) {
+    const int y = y0 + tid;
+    compact(y, y < r ? S[y] : INFINITY, y < r ? complete[y] != 0 : true);
+  }
   if (tid == 0) {
     ctl->gamma = gamma;
     ctl->n_alive = base;

@@ -86,7 +86,7 @@ struct Ctl {
   int32_t round;        // threshold round of the current iteration
   uint32_t arrivals;     // work-groups of the running score launch that have finished
   uint32_t q_next;       // batch queue: pair-kernel items of the band claimed so far
-  int32_t n_alive;        // entries of the alive list (variables with S <= gamma)
+  int32_t n_alive;        // entries of the alive list (incomplete variables with S <= gamma)
   int32_t tb_next;        // target blocks [tb_next, tb_next + ntb_next) of the next band
   int32_t ntb_next;
   int32_t iter_bands;     // bands run in the current iteration
@@ -155,7 +155,7 @@ struct Dev {
   double* Terrp = nullptr;
   double* M = nullptr;       // p x p test matrix of the iteration (NaN = not evaluated)
   double* S = nullptr;       // [p] scores (sum of min(0, M)^2 over evaluated pairs)
-  uint8_t* alive = nullptr;  // [p] S <= gamma at the last snapshot
+  uint8_t* alive = nullptr;  // [p] S <= gamma and some test not evaluated, at the last decision
   int32_t* alive_list = nullptr;  // [p] positions with alive = 1, ascending
   uint8_t* complete = nullptr;  // [p] every pair of the row evaluated
   uint8_t* pend = nullptr;   // p x p: partial sums written, M not yet formed
